@@ -1,0 +1,120 @@
+/*
+ * abjoin.h -- C ABI of the MI355X (gfx950) AB-join library, libabjoin.so.
+ *
+ * The library computes the matrix profile of an inter-time-series similarity
+ * join ("Error-bounded Approximate Time Series Joins Using Compact Dictionary
+ * Representations of Time Series", Sec. 2.1 Def. 7 and Sec. 3.2 Alg. 2): for
+ * every length-m window i of a query series it finds the nearest neighbour,
+ * under the z-normalised Euclidean distance (Def. 4), among the windows of a
+ * reference.  The reference is a dictionary stored as one concatenated series
+ * with segment offsets; only the windows that slide inside one segment take
+ * part (Def. 8), so a plain AB-join is the one-segment case.
+ *
+ * Conventions shared by every entry point
+ *   - Indexing is 0-based.  Window i of a series x of length n is
+ *     x[i .. i+m-1], i = 0 .. n-m.
+ *   - seg_bounds is a HOST array of n_seg+1 int64 offsets with
+ *     seg_bounds[0] = 0 < seg_bounds[1] < ... < seg_bounds[n_seg] = n_dict.
+ *     Reference window j is valid iff seg_bounds[s] <= j and
+ *     j + m <= seg_bounds[s+1] for some s (Def. 8).  Segments shorter than m
+ *     contribute no window.
+ *   - Distance: population mean and deviation per window; d = ||z(u) - z(v)||,
+ *     which equals sqrt(2 m (1 - rho)) and lies in [0, 2 sqrt(m)].
+ *   - Results: P_AB[i] is the distance to the nearest valid reference window,
+ *     I_AB[i] its index in the concatenated reference (ties: smallest index).
+ *     A row with no valid reference window gets P = +inf, I = -1 (Alg. 2
+ *     initialises the profile to +inf).
+ *   - Flat windows (population variance <= 1e-10 x the variance of all finite
+ *     samples of their series) are the zero vector after normalisation:
+ *     flat-flat distance 0, flat vs non-flat sqrt(m).  Reference windows with a
+ *     non-finite sample are not windows; query rows with one get P = NaN,
+ *     I = -1.  (The paper does not cover either case.)
+ *   - Device buffers are caller-owned device memory (hipMalloc or a PyTorch
+ *     CUDA tensor).  The library never frees caller memory.
+ *   - hip_stream: a hipStream_t cast to void*, NULL for the null stream.  Calls
+ *     that take a stream are asynchronous: they enqueue work and return; the
+ *     results are ready when the stream reaches that point.
+ *   - Every entry point returns an abj_status.  On ABJ_EINVAL nothing has been
+ *     enqueued and no output has been written.  abj_last_error() gives the
+ *     text of the last failure on the calling thread.  No C++ exception
+ *     crosses this interface.
+ */
+#ifndef ABJOIN_H
+#define ABJOIN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ABJ_OK = 0,
+    ABJ_EINVAL = -1,    /* invalid argument; nothing enqueued, outputs untouched */
+    ABJ_ENOMEM = -2,    /* device or host allocation failed */
+    ABJ_EHIP = -3,      /* a HIP runtime call failed; text in abj_last_error() */
+    ABJ_EBUSY = -4,     /* serving: no slot or memory for the request right now */
+    ABJ_ECANCELED = -5, /* serving: the request was cancelled */
+    ABJ_ETIMEOUT = -6,  /* serving: the wait timed out */
+    ABJ_ENOTFOUND = -7  /* serving: unknown request id */
+} abj_status;
+
+typedef enum {
+    ABJ_TIER_FP32 = 0, /* FP32 incremental-diagonal covariance, FP64 winner re-check */
+    ABJ_TIER_BF16 = 1, /* BF16 MFMA on centred, scaled windows + FP64 re-check of top-K */
+    ABJ_TIER_FP16 = 2  /* FP16 MFMA on centred, scaled windows + FP64 re-check of top-K */
+} abj_tier;
+
+typedef struct {
+    int32_t tier;     /* abj_tier */
+    int32_t refine_k; /* precision tiers: candidates re-checked per row, 1..8 (0 = 4) */
+    int32_t flags;    /* reserved, must be 0 */
+    int32_t reserved; /* must be 0 */
+} abj_opts;
+
+/* Library version, (major << 16) | minor. */
+int abj_version(void);
+
+/* Text describing the last non-OK status returned on this thread. */
+const char* abj_last_error(void);
+
+/*
+ * Select the GPU and create library state for it.  Optional: every entry
+ * point initialises the current device on first use.  Errors: ABJ_EHIP if the
+ * device does not exist.
+ */
+int abj_init(int device_ordinal);
+
+/*
+ * Per-window statistics of one series (the O(n) step before the pair loop):
+ * FP64 prefix sums of the series minus its mean give, for each window
+ * i = 0 .. n-m, the mean mu[i] and population deviation sigma[i]
+ * (Def. 4's z-normalisation).  flags[i] bit 0 = flat, bit 1 = holds a
+ * non-finite sample.  x, mu, sigma, flags: device pointers; mu and sigma hold
+ * n-m+1 doubles, flags n-m+1 bytes.  Errors: ABJ_EINVAL if m < 2, n < m or a
+ * pointer is NULL or not device memory.
+ */
+int abj_window_stats(const double* x, int64_t n, int32_t m, double* mu, double* sigma, uint8_t* flags,
+                     void* hip_stream);
+
+/*
+ * AB-join of a query against a concatenated dictionary (Alg. 2 over the
+ * windows of Def. 8; one segment = plain AB-join).
+ *   query   device, n_query doubles          dict  device, n_dict doubles
+ *   seg_bounds  host, n_seg+1 int64 offsets (see conventions)
+ *   P_AB    device, n_query-m+1 floats (out)  I_AB  device, n_query-m+1 int64 (out)
+ *   opts    NULL = FP32 tier
+ * Errors: ABJ_EINVAL if m < 2, n_query < m, n_dict < 1, n_seg < 1, bad
+ * seg_bounds, an unknown tier, refine_k outside 0..8, nonzero reserved
+ * fields, or a NULL / non-device pointer; ABJ_ENOMEM / ABJ_EHIP from the
+ * runtime.  Workspace is taken from the stream-ordered allocator on
+ * hip_stream and returned to it before the call's work completes.
+ */
+int ab_join(const double* query, int64_t n_query, const double* dict, int64_t n_dict, const int64_t* seg_bounds,
+            int32_t n_seg, int32_t m, float* P_AB, int64_t* I_AB, const abj_opts* opts, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ABJOIN_H */

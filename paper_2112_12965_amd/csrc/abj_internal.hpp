@@ -1,0 +1,105 @@
+// Internal declarations shared by the HIP sources of libabjoin.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "abjoin.h"
+
+namespace abj {
+
+// Records `code` with a printf-style message as the calling thread's last error
+// and returns `code`.
+int set_error(int code, const char* fmt, ...);
+
+#define ABJ_HIP(call)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return ::abj::set_error(ABJ_EHIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+#define ABJ_TRY(expr)              \
+    do {                           \
+        int rc_ = (expr);          \
+        if (rc_ != ABJ_OK) return rc_; \
+    } while (0)
+
+// Samples of zero padding after every centred series copy, so that the
+// register-window loads of the edge dot products never leave the buffer.
+constexpr int64_t kSeriesPad = 4096;
+
+// Flat-window threshold: population variance <= kFlatRel x series variance.
+constexpr double kFlatRel = 1e-10;
+
+// Window flag bits (also the public abj_window_stats flags).
+constexpr uint8_t kFlagFlat = 1;
+constexpr uint8_t kFlagBad = 2;
+constexpr uint8_t kFlagInvalid = 4;  // reference window that crosses a segment break
+
+// Device-side statistics of one series for one window length m.
+struct SeriesDev {
+    int64_t n = 0;         // samples
+    int64_t W = 0;         // windows, n - m + 1 (0 if n < m)
+    int32_t m = 0;
+    double* xc = nullptr;  // n + kSeriesPad: x - mean(x), non-finite -> 0, zero tail
+    double* mu = nullptr;  // W: window mean of xc
+    double* sig = nullptr; // W: window population deviation
+    float2* dfdg = nullptr;// W: {df(i), dg(i)} for the diagonal recurrence (last entry 0)
+    float4* col = nullptr; // W: {df, dg, 1/sigma or 0 when excluded, 0}
+    uint8_t* flags = nullptr;  // W
+    double* scal = nullptr;    // device scalars: [0] mean, [1] variance, [2] finite count
+    unsigned long long* first = nullptr;  // [0] first valid flat window, [1] first valid window (~0 = none)
+};
+
+// Stream-ordered scratch arena: one hipMallocAsync block carved into aligned
+// pieces, released with hipFreeAsync on the same stream.
+class Arena {
+  public:
+    explicit Arena(hipStream_t s) : stream_(s) {}
+    ~Arena();
+    void reserve(size_t bytes) { need_ += (bytes + 255) & ~size_t(255); }
+    int commit();
+    template <class T>
+    T* take(size_t count) {
+        size_t b = (count * sizeof(T) + 255) & ~size_t(255);
+        if (used_ + b > need_) abort_overflow(used_ + b, need_);
+        char* p = base_ + used_;
+        used_ += b;
+        return reinterpret_cast<T*>(p);
+    }
+    size_t size() const { return need_; }
+
+  private:
+    [[noreturn]] static void abort_overflow(size_t want, size_t have);
+    hipStream_t stream_;
+    char* base_ = nullptr;
+    size_t need_ = 0, used_ = 0;
+};
+
+// Bytes of scratch that stats_compute needs for a series of n samples.
+size_t stats_scratch_bytes(int64_t n, int64_t W);
+
+// Carves the SeriesDev arrays for (n, m) out of the arena (after commit()).
+void stats_carve(Arena& a, int64_t n, int32_t m, SeriesDev* s);
+
+// Runs the statistics pipeline: centred copy, FP64 prefix sums, per-window
+// mean / deviation / flags, recurrence terms and column records.  When
+// seg_bounds_dev is non-null the windows crossing a segment break are marked
+// invalid and first-flat / first-valid indices are computed.
+int stats_compute(const double* x, SeriesDev* s, const int64_t* seg_bounds_dev, int32_t n_seg, Arena& a,
+                  hipStream_t stream);
+
+// FP32 diagonal join of all valid query windows against all valid reference
+// windows; writes one packed (score, index) key per query row.
+int join_fp32_launch(const SeriesDev& A, const SeriesDev& B, unsigned long long* keys, hipStream_t stream);
+
+// Turns packed keys into P (FP64 re-check, flat conventions) and I.
+int finalize_launch(const SeriesDev& A, const SeriesDev& B, const unsigned long long* keys, float* P, int64_t* I,
+                    hipStream_t stream);
+
+int fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t stream);
+
+int ensure_device();
+
+}  // namespace abj

@@ -1,0 +1,199 @@
+// extern "C" entry points of libabjoin.so: argument validation, workspace,
+// and the launch sequence of each call.  See include/abjoin.h for the contract.
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <mutex>
+
+#include "abj_internal.hpp"
+
+namespace abj {
+
+namespace {
+thread_local char g_err[512] = "";
+std::mutex g_init_mu;
+int g_inited_dev[64] = {0};
+}  // namespace
+
+int set_error(int code, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+Arena::~Arena()
+{
+    if (base_) (void)hipFreeAsync(base_, stream_);
+}
+
+void Arena::abort_overflow(size_t want, size_t have)
+{
+    fprintf(stderr, "abjoin: internal workspace overflow (%zu > %zu bytes)\n", want, have);
+    abort();
+}
+
+int Arena::commit()
+{
+    if (need_ == 0) return ABJ_OK;
+    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&base_), need_, stream_);
+    if (e != hipSuccess) {
+        base_ = nullptr;
+        (void)hipGetLastError();
+        return set_error(e == hipErrorOutOfMemory ? ABJ_ENOMEM : ABJ_EHIP, "workspace of %zu bytes: %s", need_,
+                         hipGetErrorString(e));
+    }
+    return ABJ_OK;
+}
+
+int ensure_device()
+{
+    int dev = 0;
+    ABJ_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return set_error(ABJ_EHIP, "device ordinal %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_init_mu);
+    if (!g_inited_dev[dev]) {
+        // Keep stream-ordered workspace cached between calls instead of
+        // returning it to the driver at every synchronisation.
+        hipMemPool_t pool;
+        ABJ_HIP(hipDeviceGetDefaultMemPool(&pool, dev));
+        uint64_t thr = ~0ull;
+        ABJ_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr));
+        g_inited_dev[dev] = 1;
+    }
+    return ABJ_OK;
+}
+
+namespace {
+
+// Checks that [p, p + bytes) lies inside one device (or managed) allocation.
+int check_dev_buf(const void* p, size_t bytes, const char* name)
+{
+    if (!p) return set_error(ABJ_EINVAL, "%s is NULL", name);
+    hipPointerAttribute_t at;
+    hipError_t e = hipPointerGetAttributes(&at, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(ABJ_EINVAL, "%s is not device memory", name);
+    }
+    if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged)
+        return set_error(ABJ_EINVAL, "%s is not device memory", name);
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    e = hipMemGetAddressRange(&base, &size, const_cast<void*>(p));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return ABJ_OK;  // range unknown (e.g. managed): trust the caller
+    }
+    const char* b = reinterpret_cast<const char*>(base);
+    const char* q = reinterpret_cast<const char*>(p);
+    if (q < b || (size_t)(q - b) + bytes > size)
+        return set_error(ABJ_EINVAL, "%s: %zu bytes do not fit in its allocation", name, bytes);
+    return ABJ_OK;
+}
+
+int check_bounds(const int64_t* sb, int32_t n_seg, int64_t n_dict)
+{
+    if (!sb) return set_error(ABJ_EINVAL, "seg_bounds is NULL");
+    if (n_seg < 1) return set_error(ABJ_EINVAL, "n_seg must be >= 1 (got %d)", n_seg);
+    if (sb[0] != 0) return set_error(ABJ_EINVAL, "seg_bounds[0] must be 0");
+    if (sb[n_seg] != n_dict) return set_error(ABJ_EINVAL, "seg_bounds[n_seg] must equal n_dict");
+    for (int32_t s = 0; s < n_seg; ++s)
+        if (sb[s + 1] <= sb[s]) return set_error(ABJ_EINVAL, "seg_bounds must be strictly increasing (at %d)", s);
+    return ABJ_OK;
+}
+
+constexpr int32_t kMaxM = 4096;
+constexpr int64_t kMaxN = (1LL << 31) - 1;
+
+}  // namespace
+
+int stats_export(const SeriesDev& s, double* mu, double* sig, uint8_t* flags, hipStream_t stream);
+
+}  // namespace abj
+
+using namespace abj;
+
+extern "C" int abj_version(void) { return (0 << 16) | 1; }
+
+extern "C" const char* abj_last_error(void) { return g_err; }
+
+extern "C" int abj_init(int device_ordinal)
+{
+    int count = 0;
+    ABJ_HIP(hipGetDeviceCount(&count));
+    if (device_ordinal < 0 || device_ordinal >= count)
+        return set_error(ABJ_EHIP, "device %d does not exist (%d visible)", device_ordinal, count);
+    ABJ_HIP(hipSetDevice(device_ordinal));
+    return ensure_device();
+}
+
+extern "C" int abj_window_stats(const double* x, int64_t n, int32_t m, double* mu, double* sigma, uint8_t* flags,
+                                void* hip_stream)
+{
+    if (m < 2 || m > kMaxM) return set_error(ABJ_EINVAL, "m must be in [2, %d] (got %d)", kMaxM, m);
+    if (n < m || n > kMaxN) return set_error(ABJ_EINVAL, "n must be in [m, 2^31-1] (got %lld)", (long long)n);
+    const int64_t W = n - m + 1;
+    ABJ_TRY(check_dev_buf(x, sizeof(double) * (size_t)n, "x"));
+    ABJ_TRY(check_dev_buf(mu, sizeof(double) * (size_t)W, "mu"));
+    ABJ_TRY(check_dev_buf(sigma, sizeof(double) * (size_t)W, "sigma"));
+    ABJ_TRY(check_dev_buf(flags, (size_t)W, "flags"));
+    ABJ_TRY(ensure_device());
+    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+    Arena ar(stream);
+    ar.reserve(stats_scratch_bytes(n, W));
+    ABJ_TRY(ar.commit());
+    SeriesDev s;
+    stats_carve(ar, n, m, &s);
+    ABJ_TRY(stats_compute(x, &s, nullptr, 0, ar, stream));
+    return stats_export(s, mu, sigma, flags, stream);
+}
+
+extern "C" int ab_join(const double* query, int64_t n_query, const double* dict, int64_t n_dict,
+                       const int64_t* seg_bounds, int32_t n_seg, int32_t m, float* P_AB, int64_t* I_AB,
+                       const abj_opts* opts, void* hip_stream)
+{
+    // ---- validation: nothing is enqueued or written before this passes ----
+    abj_opts o = {ABJ_TIER_FP32, 0, 0, 0};
+    if (opts) o = *opts;
+    if (o.tier != ABJ_TIER_FP32)
+        return set_error(ABJ_EINVAL, "tier %d is not available", o.tier);
+    if (o.refine_k < 0 || o.refine_k > 8) return set_error(ABJ_EINVAL, "refine_k must be in 0..8");
+    if (o.flags != 0 || o.reserved != 0) return set_error(ABJ_EINVAL, "opts.flags and opts.reserved must be 0");
+    if (m < 2 || m > kMaxM) return set_error(ABJ_EINVAL, "m must be in [2, %d] (got %d)", kMaxM, m);
+    if (n_query < m || n_query > kMaxN)
+        return set_error(ABJ_EINVAL, "n_query must be in [m, 2^31-1] (got %lld)", (long long)n_query);
+    if (n_dict < 1 || n_dict > kMaxN)
+        return set_error(ABJ_EINVAL, "n_dict must be in [1, 2^31-1] (got %lld)", (long long)n_dict);
+    ABJ_TRY(check_bounds(seg_bounds, n_seg, n_dict));
+    const int64_t WA = n_query - m + 1;
+    const int64_t WB = n_dict >= m ? n_dict - m + 1 : 0;
+    ABJ_TRY(check_dev_buf(query, sizeof(double) * (size_t)n_query, "query"));
+    ABJ_TRY(check_dev_buf(dict, sizeof(double) * (size_t)n_dict, "dict"));
+    ABJ_TRY(check_dev_buf(P_AB, sizeof(float) * (size_t)WA, "P_AB"));
+    ABJ_TRY(check_dev_buf(I_AB, sizeof(int64_t) * (size_t)WA, "I_AB"));
+    ABJ_TRY(ensure_device());
+
+    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+    Arena ar(stream);
+    ar.reserve(stats_scratch_bytes(n_query, WA));
+    ar.reserve(stats_scratch_bytes(n_dict, WB));
+    ar.reserve(sizeof(unsigned long long) * (size_t)WA);
+    ar.reserve(sizeof(int64_t) * (size_t)(n_seg + 1));
+    ABJ_TRY(ar.commit());
+    SeriesDev A, B;
+    stats_carve(ar, n_query, m, &A);
+    stats_carve(ar, n_dict, m, &B);
+    unsigned long long* keys = ar.take<unsigned long long>((size_t)WA);
+    int64_t* dbounds = ar.take<int64_t>((size_t)(n_seg + 1));
+    ABJ_HIP(hipMemcpyAsync(dbounds, seg_bounds, sizeof(int64_t) * (size_t)(n_seg + 1), hipMemcpyHostToDevice, stream));
+    ABJ_TRY(stats_compute(query, &A, nullptr, 0, ar, stream));
+    ABJ_TRY(stats_compute(dict, &B, dbounds, n_seg, ar, stream));
+    ABJ_TRY(fill_u64(keys, WA, 0ull, stream));
+    ABJ_TRY(join_fp32_launch(A, B, keys, stream));
+    return finalize_launch(A, B, keys, P_AB, I_AB, stream);
+}

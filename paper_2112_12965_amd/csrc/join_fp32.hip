@@ -1,0 +1,287 @@
+// FP32 AB-join by incremental diagonal covariance (the pair loop of Alg. 2).
+//
+// For query window i and reference window j let
+//   cov(i, j) = sum_k (a[i+k] - mu_a(i)) (b[j+k] - mu_b(j)).
+// Then rho(i, j) = cov / (m sigma_a(i) sigma_b(j)) and the z-normalised
+// distance is d = sqrt(2 m (1 - rho)), so the nearest neighbour of row i is the
+// column with the largest cov(i, j) / sigma_b(j) (the row factor drops out).
+// Along a diagonal the covariance obeys an O(1) update (derived from the
+// definition; see the statistics kernels for df and dg):
+//   cov(i+1, j+1) = cov(i, j) + df_a(i) dg_b(j) + df_b(j) dg_a(i).
+//
+// Work decomposition (one 64-lane wave per tile, no inter-wave traffic):
+//   * a tile is 1024 query rows x 1024 reference columns;
+//   * lane l owns rows i0 + 16 l .. i0 + 16 l + 15 and keeps their covariance,
+//     running best score and best column in registers;
+//   * the wave walks the tile's columns in order; a column's terms
+//     {df_b, dg_b, 1/sigma_b} are the same for all lanes, so they come from
+//     scalar loads;
+//   * cov(i, j) needs cov(i-1, j-1): for a lane's first row that is the last
+//     row of the lane below, moved across with one DPP wave_shr:1; lane 0 takes
+//     the tile's top edge instead;
+//   * the tile's left column and top row are exact FP64 dot products (so FP32
+//     drift is bounded by the tile size); columns excluded by the segment mask
+//     or the flat rule skip the scoring but still advance the recurrence;
+//   * at the end each row's best (score, column) is merged across tiles with a
+//     64-bit atomic max on an order-preserving key (ties -> smallest column).
+#include <math.h>
+
+#include "abj_internal.hpp"
+
+namespace abj {
+
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kR = 16;                  // query rows per lane
+constexpr int kBandRows = kR * kWave;   // query rows per tile
+constexpr int kTC = 1024;               // reference columns per tile
+constexpr int kQ = kTC / kWave;         // top-edge columns per lane
+constexpr int kDppWaveShr1 = 0x138;     // DPP control: whole-wave shift right by one lane
+constexpr int kG = 8;                   // width of the FP64 edge dot-product groups
+
+// acc[g] = sum_{k<m} w[k] * x[base + g + k] for g < G.  x is read through a
+// G-entry register window that slides by one sample per k (one load per G FMAs).
+template <int G>
+__device__ inline void sliding_dots(const double* __restrict__ x, int64_t base, const double* w, int m,
+                                    double (&acc)[G])
+{
+    double win[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        acc[g] = 0.0;
+        win[g] = x[base + g];
+    }
+    int k0 = 0;
+    // Invariant at the top of each block: win[s] holds x[base + k0 + s].
+    for (; k0 + G <= m; k0 += G) {
+#pragma unroll
+        for (int kk = 0; kk < G; ++kk) {
+            const double wk = w[k0 + kk];
+#pragma unroll
+            for (int g = 0; g < G; ++g) acc[g] = fma(wk, win[(kk + g) % G], acc[g]);
+            win[kk] = x[base + k0 + kk + G];
+        }
+    }
+    for (int k = k0; k < m; ++k) {
+        const double wk = w[k];
+#pragma unroll
+        for (int g = 0; g < G; ++g) acc[g] = fma(wk, x[base + g + k], acc[g]);
+    }
+}
+
+__device__ inline double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+__host__ __device__ inline size_t edge_offset(int m) { return ((size_t)m * sizeof(double) + 15) & ~size_t(15); }
+
+__device__ inline unsigned long long pack_key(float s, int j)
+{
+    unsigned u = __float_as_uint(s);
+    u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+    return ((unsigned long long)u << 32) | (unsigned long long)(0xFFFFFFFFu - (unsigned)j);
+}
+
+// One sweep step over column j.  On entry logical row r of this lane lives in
+// register slot (r - U) mod kR; the step writes new row r over old row r-1
+// (in place, no register moves), so on exit row r lives in slot (r - U - 1).
+template <int U, bool kGuard>
+__device__ __forceinline__ bool sweep_step(int64_t j, int64_t jend, const float4* __restrict__ bcol, float e,
+                                           float (&S)[kR], const float (&pf)[kR], const float (&pg)[kR],
+                                           float (&best)[kR], int (&bidx)[kR], float4& prev)
+{
+    if (kGuard && j >= jend) return false;
+    const float4 cur = bcol[j];
+    // lanes 1..63 receive the last row of the lane below; lane 0 keeps the edge
+    const float t = __int_as_float(__builtin_amdgcn_update_dpp(
+        __float_as_int(e), __float_as_int(S[(kR - 1 - U) & (kR - 1)]), kDppWaveShr1, 0xf, 0xf, false));
+#pragma unroll
+    for (int r = kR - 1; r >= 1; --r) {
+        float& c = S[(r - 1 - U) & (kR - 1)];
+        c = fmaf(pg[r], prev.x, fmaf(pf[r], prev.y, c));
+    }
+    S[(kR - 1 - U) & (kR - 1)] = fmaf(pg[0], prev.x, fmaf(pf[0], prev.y, t));
+    if (cur.z != 0.f) {
+#pragma unroll
+        for (int r = 0; r < kR; ++r) {
+            const float sc = S[(r - 1 - U) & (kR - 1)] * cur.z;
+            const bool up = sc > best[r];
+            // improvements are rare after the first columns: branch only when
+            // some lane improves this row
+            if (__builtin_expect(__builtin_amdgcn_ballot_w64(up) != 0, 0)) {
+                // keeps this a real branch: without it the compiler turns the
+                // update into unconditional selects on every step
+                asm volatile("" ::: "memory");
+                best[r] = up ? sc : best[r];
+                bidx[r] = up ? (int)j : bidx[r];
+            }
+        }
+    }
+    prev = cur;
+    return true;
+}
+
+// kR consecutive steps starting at column jb; edge values e[0..kR) belong to
+// columns jb .. jb+kR-1.
+template <bool kGuard>
+__device__ __forceinline__ void sweep_block(int64_t jb, int64_t jend, const float4* __restrict__ bcol,
+                                            const float (&e)[kR], float (&S)[kR], const float (&pf)[kR],
+                                            const float (&pg)[kR], float (&best)[kR], int (&bidx)[kR],
+                                            float4& prev)
+{
+#define ABJ_STEP(u) \
+    if (!sweep_step<u, kGuard>(jb + u, jend, bcol, e[u], S, pf, pg, best, bidx, prev)) return;
+    ABJ_STEP(0) ABJ_STEP(1) ABJ_STEP(2) ABJ_STEP(3) ABJ_STEP(4) ABJ_STEP(5) ABJ_STEP(6) ABJ_STEP(7)
+    ABJ_STEP(8) ABJ_STEP(9) ABJ_STEP(10) ABJ_STEP(11) ABJ_STEP(12) ABJ_STEP(13) ABJ_STEP(14) ABJ_STEP(15)
+#undef ABJ_STEP
+}
+
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void k_join_fp32(
+    const double* __restrict__ axc, const double* __restrict__ amu, const float2* __restrict__ adfdg, int64_t WA,
+    const double* __restrict__ bxc, const double* __restrict__ bmu, const float4* __restrict__ bcol, int64_t WB,
+    int m, int nchunks, unsigned long long* __restrict__ keys)
+{
+    extern __shared__ double lds[];
+    double* wv = lds;                                  // m doubles: one centred window
+    // kTC + kR floats, 16-byte aligned: edge[t] = cov(i0, j0 + 1 + t)
+    float* edge = reinterpret_cast<float*>(reinterpret_cast<char*>(lds) + edge_offset(m));
+
+    const int lane = threadIdx.x;
+    const int64_t band = blockIdx.x / nchunks;
+    const int64_t chunk = blockIdx.x - band * nchunks;
+    const int64_t i0 = band * kBandRows;
+    const int64_t j0 = chunk * kTC;
+    const int64_t jend = j0 + kTC < WB ? j0 + kTC : WB;
+    const int64_t ibase = i0 + (int64_t)lane * kR;
+
+    // ---- top edge: cov(i0, j) for the tile's columns ------------------------
+    {
+        const double na = amu[i0];
+        double part = 0.0;
+        for (int k = lane; k < m; k += kWave) {
+            const double v = axc[i0 + k] - na;
+            wv[k] = v;
+            part += v;
+        }
+        const double sa = wave_sum(part);
+        __syncthreads();
+        const int64_t cbase = j0 + (int64_t)lane * kQ;
+#pragma unroll
+        for (int h = 0; h < kQ; h += kG) {
+            double acc[kG];
+            sliding_dots<kG>(bxc, cbase + h, wv, m, acc);
+#pragma unroll
+            for (int g = 0; g < kG; ++g) {
+                const int64_t j = cbase + h + g;
+                const double mb = j < WB ? bmu[j] : 0.0;
+                const int t = lane * kQ + h + g - 1;  // edge[] starts at column j0 + 1
+                if (t >= 0) edge[t] = (float)(acc[g] - mb * sa);
+            }
+        }
+        __syncthreads();
+    }
+
+    float S[kR];
+    // ---- left edge: cov(i, j0) for this lane's rows, exact in FP64 ----------
+    {
+        const double nb = bmu[j0];
+        double part = 0.0;
+        for (int k = lane; k < m; k += kWave) {
+            const double v = bxc[j0 + k] - nb;
+            wv[k] = v;
+            part += v;
+        }
+        const double sb = wave_sum(part);
+        __syncthreads();
+        // cov = sum_k (a - mu_a) bhat_k = sum_k a bhat_k - mu_a sum_k bhat_k
+#pragma unroll
+        for (int h = 0; h < kR; h += kG) {
+            double acc[kG];
+            sliding_dots<kG>(axc, ibase + h, wv, m, acc);
+#pragma unroll
+            for (int g = 0; g < kG; ++g) {
+                const int64_t i = ibase + h + g;
+                const double ma = i < WA ? amu[i] : 0.0;
+                S[h + g] = (float)(acc[g] - ma * sb);
+            }
+        }
+        __syncthreads();
+    }
+    // ---- main sweep -----------------------------------------------------------
+    float pf[kR], pg[kR], best[kR];
+    int bidx[kR];
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+        const int64_t i = ibase + r;
+        // terms of the step from row i-1 into row i; zero for the tile's top
+        // row (lane 0, r 0) so that lane 0 takes the top edge unchanged
+        float2 t = make_float2(0.f, 0.f);
+        if (i > i0 && i - 1 < WA - 1) t = adfdg[i - 1];
+        pf[r] = t.x;
+        pg[r] = t.y;
+        best[r] = -INFINITY;
+        bidx[r] = -1;
+    }
+    {
+        const float inv = bcol[j0].z;
+        if (inv != 0.f) {
+#pragma unroll
+            for (int r = 0; r < kR; ++r) {
+                best[r] = S[r] * inv;
+                bidx[r] = (int)j0;
+            }
+        }
+    }
+    float4 prev = bcol[j0];
+    const int64_t nfull = (jend - j0 - 1) / kR;  // full 16-column blocks after column j0
+    for (int64_t b = 0; b < nfull; ++b) {
+        const int64_t jb = j0 + 1 + b * kR;
+        float e[kR];
+        const float4* e4 = reinterpret_cast<const float4*>(edge + b * kR);
+#pragma unroll
+        for (int q = 0; q < kR / 4; ++q) {
+            const float4 v = e4[q];
+            e[4 * q] = v.x;
+            e[4 * q + 1] = v.y;
+            e[4 * q + 2] = v.z;
+            e[4 * q + 3] = v.w;
+        }
+        sweep_block<false>(jb, jend, bcol, e, S, pf, pg, best, bidx, prev);
+    }
+    {
+        const int64_t jb = j0 + 1 + nfull * kR;
+        if (jb < jend) {
+            float e[kR];
+#pragma unroll
+            for (int u = 0; u < kR; ++u) e[u] = edge[nfull * kR + u];
+            sweep_block<true>(jb, jend, bcol, e, S, pf, pg, best, bidx, prev);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+        const int64_t i = ibase + r;
+        if (i < WA && bidx[r] >= 0) atomicMax(&keys[i], pack_key(best[r], bidx[r]));
+    }
+}
+
+}  // namespace
+
+int join_fp32_launch(const SeriesDev& A, const SeriesDev& B, unsigned long long* keys, hipStream_t stream)
+{
+    if (A.W <= 0 || B.W <= 0) return ABJ_OK;
+    const int64_t nbands = (A.W + kBandRows - 1) / kBandRows;
+    const int64_t nchunks = (B.W + kTC - 1) / kTC;
+    const int64_t blocks = nbands * nchunks;
+    if (blocks > 0x7fffffffLL) return set_error(ABJ_EINVAL, "join too large for one launch (%lld tiles)", (long long)blocks);
+    const size_t lds = edge_offset((int)A.m) + sizeof(float) * (kTC + kR);
+    hipLaunchKernelGGL(k_join_fp32, dim3((unsigned)blocks), dim3(kWave), lds, stream, A.xc, A.mu, A.dfdg, A.W, B.xc,
+                       B.mu, B.col, B.W, (int)A.m, (int)nchunks, keys);
+    ABJ_HIP(hipGetLastError());
+    return ABJ_OK;
+}
+
+}  // namespace abj

@@ -1,0 +1,182 @@
+"""GPU parity of the FP32 tier against the FP64 oracle, through the C-ABI.
+
+Tolerance (FP32 tier): |P_gpu - P_oracle| <= 1e-3 per row; I_AB equal where the
+oracle's best-to-second gap exceeds 1e-3; every returned neighbour within 1e-3
+of the best.  Sizes span several 1024 x 1024 tiles with ragged tails.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import _parity
+from paper_2112_12965_amd import abjoin, synth
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-3
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def run(q, d, bounds, m, tier="fp32"):
+    P, I = abjoin.ab_join(dev(q), dev(d), bounds, m, tier=tier)
+    torch.cuda.synchronize()
+    return P.cpu().numpy().astype(np.float64), I.cpu().numpy()
+
+
+def full_check(orc, q, d, bounds, m, tier="fp32", tol=TOL):
+    print(f"[case] n_q={len(q)} n_d={len(d)} segs={len(bounds) - 1} m={m} tier={tier}", flush=True)
+    P, I = run(q, d, bounds, m, tier)
+    Po, Io, P2o = orc.ab_join(q, d, bounds, m, second=True)
+    return _parity.compare(P, I, Po, Io, P2o, tol, orc, q, d, m)
+
+
+def test_window_stats_match_oracle(orc):
+    x = synth.random_walk(200_000, synth.rng_for(90, 0))
+    x[5000:5300] = 7.0  # flat stretch
+    for m in (2, 100, 256):
+        mu, sd, fl = abjoin.window_stats(dev(x), m)
+        torch.cuda.synchronize()
+        omu, osd, oflat, obad = orc.window_stats(x, m)
+        np.testing.assert_allclose(mu.cpu().numpy(), omu, rtol=1e-12, atol=1e-9)
+        nf = ~oflat
+        np.testing.assert_allclose(sd.cpu().numpy()[nf], osd[nf], rtol=1e-9)
+        f = fl.cpu().numpy()
+        np.testing.assert_array_equal((f & abjoin.FLAG_FLAT) != 0, oflat)
+        np.testing.assert_array_equal((f & abjoin.FLAG_BAD) != 0, obad)
+
+
+def test_small_random_walk_m100(orc):
+    w = synth.WORKLOADS["rw2k_m100"]()
+    st = full_check(orc, w["query"], w["dict"], w["bounds"], w["m"])
+    print(st)
+
+
+@pytest.mark.parametrize("m", [2, 16, 100])
+def test_multi_tile_ragged_segments(orc, m):
+    rng = np.random.default_rng(1000 + m)
+    q = synth.random_walk(5003, rng)
+    d = synth.random_walk(3001, rng)
+    bounds = [0, 1000, 1000 + max(m - 1, 1), 2050, 3001]  # includes a segment too short for any window
+    full_check(orc, q, d, bounds, m)
+
+
+def test_ecg_dictionary_m256(orc):
+    rng = synth.rng_for(91, 0)
+    q = synth.ecg_like(4096, rng, n_anomalies=3)
+    src = synth.ecg_like(40000, synth.rng_for(91, 1))
+    d, bounds, _ = synth.cut_dictionary(src, 8, 2000, synth.rng_for(91, 2))
+    full_check(orc, q, d, bounds, 256)
+
+
+def test_planted_copies_and_signs(orc):
+    rng = np.random.default_rng(5)
+    m = 64
+    d = synth.random_walk(6000, rng)
+    q = synth.random_walk(4000, rng)
+    q[100:100 + m] = 2.0 * d[3333:3333 + m] + 11.0
+    q[2000:2000 + m] = -3.0 * d[777:777 + m]
+    P, I = run(q, d, [0, len(d)], m)
+    assert P[100] < 1e-3 and I[100] == 3333
+    assert np.all((P >= 0) & (P <= 2 * math.sqrt(m) + 1e-3))
+    full_check(orc, q, d, [0, len(d)], m)
+
+
+def test_flat_and_nonfinite_conventions(orc):
+    m = 8
+    rng = np.random.default_rng(19)
+    q = rng.standard_normal(3000)
+    q[10:30] = 2.5
+    q[45] = np.nan
+    d = rng.standard_normal(2500)
+    d[500:560] = -1.0
+    d[5] = np.inf
+    full_check(orc, q, d, [0, 1200, 2500], m)
+    d2 = d.copy()
+    d2[500:560] = rng.standard_normal(60)
+    full_check(orc, q, d2, [0, 1200, 2500], m)
+
+
+def test_degenerate_inputs(orc):
+    rng = np.random.default_rng(23)
+    q = rng.standard_normal(50)
+    # no segment long enough: every row is +inf / -1 (Alg. 2's initialisation)
+    P, I = run(q, rng.standard_normal(30), [0, 10, 20, 30], 12)
+    assert np.all(np.isinf(P)) and np.all(I == -1)
+    # reference shorter than m
+    P, I = run(q, rng.standard_normal(5), [0, 5], 12)
+    assert np.all(np.isinf(P)) and np.all(I == -1)
+    # a single query window, a single reference window
+    full_check(orc, q[:12], rng.standard_normal(12), [0, 12], 12)
+
+
+def test_rejects_bad_output_buffers_without_writing():
+    """Undersized raw hipMalloc output and host-memory output are rejected with
+    ABJ_EINVAL before any work is enqueued."""
+    import ctypes
+
+    hip = ctypes.CDLL("libamdhip64.so")
+    q = dev(np.random.default_rng(1).standard_normal(500))
+    m, W = 16, 485
+    raw_p, raw_i = ctypes.c_void_p(), ctypes.c_void_p()
+    assert hip.hipMalloc(ctypes.byref(raw_p), ctypes.c_size_t(4 * 400)) == 0
+    assert hip.hipMalloc(ctypes.byref(raw_i), ctypes.c_size_t(8 * W)) == 0
+    try:
+        assert hip.hipMemset(raw_p, ctypes.c_int(0x7F), ctypes.c_size_t(4 * 400)) == 0
+        b = np.array([0, 500], dtype=np.int64)
+        L = abjoin.lib()
+        rc = L.ab_join(q.data_ptr(), 500, q.data_ptr(), 500, b.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 1, m,
+                       raw_p, raw_i, None, None)
+        assert rc == abjoin.ABJ_EINVAL and "P_AB" in abjoin.last_error()
+        host = np.full(W, 7.0, dtype=np.float32)
+        rc = L.ab_join(q.data_ptr(), 500, q.data_ptr(), 500, b.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 1, m,
+                       host.ctypes.data, raw_i, None, None)
+        assert rc == abjoin.ABJ_EINVAL and "device memory" in abjoin.last_error()
+        assert np.all(host == 7.0)
+        torch.cuda.synchronize()
+        back = np.empty(400, dtype=np.float32)
+        assert hip.hipMemcpy(back.ctypes.data_as(ctypes.c_void_p), raw_p, ctypes.c_size_t(4 * 400), 2) == 0
+        assert np.all(back.view(np.uint32) == 0x7F7F7F7F)
+    finally:
+        hip.hipFree(raw_p)
+        hip.hipFree(raw_i)
+
+
+def test_deterministic():
+    rng = np.random.default_rng(2)
+    q, d = dev(synth.random_walk(20000, rng)), dev(synth.random_walk(9000, rng))
+    a = abjoin.ab_join(q, d, [0, 9000], 50)
+    b = abjoin.ab_join(q, d, [0, 9000], 50)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+def test_dictionary_workload_sampled_rows(orc):
+    """The benchmark workload at full size: 131,072-sample ECG-like query against
+    16 x 2,000 dictionary segments, m = 256; oracle on sampled rows."""
+    w = synth.WORKLOADS["ecg131k_dict16x2000_m256"]()
+    q, d, b, m = w["query"], w["dict"], w["bounds"], w["m"]
+    print(f"[case] dictionary workload n_q={len(q)} n_d={len(d)} m={m}", flush=True)
+    P, I = run(q, d, b, m)
+    rows = np.unique(np.concatenate([
+        np.random.default_rng(3).choice(len(P), 384, replace=False),
+        np.clip(w["anomalies"], 0, len(P) - 1), [0, len(P) - 1]]))
+    Po, Io, P2o = orc.ab_join(q, d, b, m, rows=rows, second=True)
+    st = _parity.compare(P[rows], I[rows], Po, Io, P2o, TOL, orc, q, d, m, rows=rows)
+    print(st)
+
+
+def test_large_random_walk_sampled_rows(orc):
+    """1,048,576-sample random walks, m = 128, at full size; oracle on sampled rows."""
+    w = synth.WORKLOADS["rw1m_m128"]()
+    q, d, b, m = w["query"], w["dict"], w["bounds"], w["m"]
+    print(f"[case] large random walk n={len(q)} m={m}", flush=True)
+    P, I = run(q, d, b, m)
+    rows = np.unique(np.concatenate([np.random.default_rng(4).choice(len(P), 96, replace=False),
+                                     [0, 1023, 1024, len(P) - 1]]))
+    Po, Io, P2o = orc.ab_join(q, d, b, m, rows=rows, second=True)
+    st = _parity.compare(P[rows], I[rows], Po, Io, P2o, TOL, orc, q, d, m, rows=rows)
+    print(st)

@@ -113,6 +113,17 @@ int abj_window_stats(const double* x, int64_t n, int32_t m, double* mu, double* 
 int ab_join(const double* query, int64_t n_query, const double* dict, int64_t n_dict, const int64_t* seg_bounds,
             int32_t n_seg, int32_t m, float* P_AB, int64_t* I_AB, const abj_opts* opts, void* hip_stream);
 
+/*
+ * Benchmark timing.  While enabled (on != 0), every join records a HIP event
+ * pair around its pair-loop kernel on the call's stream.  abj_profile_read
+ * waits for the recorded events, returns the summed kernel milliseconds, the
+ * number of launches and the number of valid (query window, reference window)
+ * pairs they covered since the previous read, and clears the record.  Any
+ * output pointer may be NULL.  Errors: ABJ_EHIP from the event calls.
+ */
+int abj_profile_enable(int on);
+int abj_profile_read(double* kernel_ms, int64_t* launches, int64_t* pairs);
+
 #ifdef __cplusplus
 }
 #endif

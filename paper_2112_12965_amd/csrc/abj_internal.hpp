@@ -42,6 +42,7 @@ struct SeriesDev {
     int64_t n = 0;         // samples
     int64_t W = 0;         // windows, n - m + 1 (0 if n < m)
     int32_t m = 0;
+    int64_t nvalid = 0;    // reference side: windows inside one segment (host-computed)
     double* xc = nullptr;  // n + kSeriesPad: x - mean(x), non-finite -> 0, zero tail
     double* mu = nullptr;  // W: window mean of xc
     double* sig = nullptr; // W: window population deviation
@@ -101,5 +102,14 @@ int finalize_launch(const SeriesDev& A, const SeriesDev& B, const unsigned long 
 int fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t stream);
 
 int ensure_device();
+
+// Benchmark timing hooks (no-ops unless abj_profile_enable(1) was called):
+// prof_begin records a start event on the stream, prof_end the stop event and
+// the number of valid pairs the launch covers.
+struct ProfMark {
+    hipEvent_t start = nullptr;
+};
+int prof_begin(ProfMark* mark, hipStream_t stream);
+int prof_end(ProfMark* mark, hipStream_t stream, int64_t pairs);
 
 }  // namespace abj

@@ -5,7 +5,9 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <atomic>
 #include <mutex>
+#include <vector>
 
 #include "abj_internal.hpp"
 
@@ -15,7 +17,36 @@ namespace {
 thread_local char g_err[512] = "";
 std::mutex g_init_mu;
 int g_inited_dev[64] = {0};
+
+struct ProfRecord {
+    hipEvent_t start, stop;
+    int64_t pairs;
+};
+std::atomic<int> g_prof_on{0};
+std::mutex g_prof_mu;
+std::vector<ProfRecord> g_prof;
 }  // namespace
+
+int prof_begin(ProfMark* mark, hipStream_t stream)
+{
+    mark->start = nullptr;
+    if (!g_prof_on.load()) return ABJ_OK;
+    ABJ_HIP(hipEventCreate(&mark->start));
+    ABJ_HIP(hipEventRecord(mark->start, stream));
+    return ABJ_OK;
+}
+
+int prof_end(ProfMark* mark, hipStream_t stream, int64_t pairs)
+{
+    if (!mark->start) return ABJ_OK;
+    hipEvent_t stop;
+    ABJ_HIP(hipEventCreate(&stop));
+    ABJ_HIP(hipEventRecord(stop, stream));
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof.push_back({mark->start, stop, pairs});
+    mark->start = nullptr;
+    return ABJ_OK;
+}
 
 int set_error(int code, const char* fmt, ...)
 {
@@ -132,6 +163,38 @@ extern "C" int abj_init(int device_ordinal)
     return ensure_device();
 }
 
+extern "C" int abj_profile_enable(int on)
+{
+    g_prof_on.store(on != 0);
+    return ABJ_OK;
+}
+
+extern "C" int abj_profile_read(double* kernel_ms, int64_t* launches, int64_t* pairs)
+{
+    std::vector<ProfRecord> recs;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        recs.swap(g_prof);
+    }
+    double ms = 0.0;
+    int64_t np = 0;
+    int rc = ABJ_OK;
+    for (auto& r : recs) {
+        float e = 0.f;
+        hipError_t st = hipEventSynchronize(r.stop);
+        if (st == hipSuccess) st = hipEventElapsedTime(&e, r.start, r.stop);
+        if (st != hipSuccess && rc == ABJ_OK) rc = set_error(ABJ_EHIP, "profile event: %s", hipGetErrorString(st));
+        ms += e;
+        np += r.pairs;
+        (void)hipEventDestroy(r.start);
+        (void)hipEventDestroy(r.stop);
+    }
+    if (kernel_ms) *kernel_ms = ms;
+    if (launches) *launches = (int64_t)recs.size();
+    if (pairs) *pairs = np;
+    return rc;
+}
+
 extern "C" int abj_window_stats(const double* x, int64_t n, int32_t m, double* mu, double* sigma, uint8_t* flags,
                                 void* hip_stream)
 {
@@ -188,6 +251,10 @@ extern "C" int ab_join(const double* query, int64_t n_query, const double* dict,
     SeriesDev A, B;
     stats_carve(ar, n_query, m, &A);
     stats_carve(ar, n_dict, m, &B);
+    for (int32_t sgi = 0; sgi < n_seg; ++sgi) {
+        const int64_t len = seg_bounds[sgi + 1] - seg_bounds[sgi];
+        if (len >= m) B.nvalid += len - m + 1;
+    }
     unsigned long long* keys = ar.take<unsigned long long>((size_t)WA);
     int64_t* dbounds = ar.take<int64_t>((size_t)(n_seg + 1));
     ABJ_HIP(hipMemcpyAsync(dbounds, seg_bounds, sizeof(int64_t) * (size_t)(n_seg + 1), hipMemcpyHostToDevice, stream));

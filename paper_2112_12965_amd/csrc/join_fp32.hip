@@ -143,7 +143,7 @@ __device__ __forceinline__ void sweep_block(int64_t jb, int64_t jend, const floa
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void k_join_fp32(
     const double* __restrict__ axc, const double* __restrict__ amu, const float2* __restrict__ adfdg, int64_t WA,
     const double* __restrict__ bxc, const double* __restrict__ bmu, const float4* __restrict__ bcol, int64_t WB,
-    int m, int nchunks, unsigned long long* __restrict__ keys)
+    int m, int nchunks, int tc, unsigned long long* __restrict__ keys)
 {
     extern __shared__ double lds[];
     double* wv = lds;                                  // m doubles: one centred window
@@ -154,8 +154,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void
     const int64_t band = blockIdx.x / nchunks;
     const int64_t chunk = blockIdx.x - band * nchunks;
     const int64_t i0 = band * kBandRows;
-    const int64_t j0 = chunk * kTC;
-    const int64_t jend = j0 + kTC < WB ? j0 + kTC : WB;
+    const int64_t j0 = chunk * tc;  // tc <= kTC columns per tile, chosen by the host to balance tiles
+    const int64_t jend = j0 + tc < WB ? j0 + tc : WB;
     const int64_t ibase = i0 + (int64_t)lane * kR;
 
     // ---- top edge: cov(i0, j) for the tile's columns ------------------------
@@ -275,13 +275,19 @@ int join_fp32_launch(const SeriesDev& A, const SeriesDev& B, unsigned long long*
     if (A.W <= 0 || B.W <= 0) return ABJ_OK;
     const int64_t nbands = (A.W + kBandRows - 1) / kBandRows;
     const int64_t nchunks = (B.W + kTC - 1) / kTC;
+    // equal chunk widths (multiple of 16) so that no tile is a sliver
+    int64_t tc = (B.W + nchunks - 1) / nchunks;
+    tc = (tc + kR - 1) / kR * kR;
+    if (tc > kTC) tc = kTC;
     const int64_t blocks = nbands * nchunks;
     if (blocks > 0x7fffffffLL) return set_error(ABJ_EINVAL, "join too large for one launch (%lld tiles)", (long long)blocks);
     const size_t lds = edge_offset((int)A.m) + sizeof(float) * (kTC + kR);
+    ProfMark mark;
+    ABJ_TRY(prof_begin(&mark, stream));
     hipLaunchKernelGGL(k_join_fp32, dim3((unsigned)blocks), dim3(kWave), lds, stream, A.xc, A.mu, A.dfdg, A.W, B.xc,
-                       B.mu, B.col, B.W, (int)A.m, (int)nchunks, keys);
+                       B.mu, B.col, B.W, (int)A.m, (int)nchunks, (int)tc, keys);
     ABJ_HIP(hipGetLastError());
-    return ABJ_OK;
+    return prof_end(&mark, stream, A.W * B.nvalid);
 }
 
 }  // namespace abj

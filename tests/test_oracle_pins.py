@@ -135,7 +135,7 @@ def test_window_stats_against_numpy(orc):
     assert not flat.any() and not bad.any()
 
 
-@settings(max_examples=40, deadline=None)
+@settings(max_examples=60, deadline=None, derandomize=True)
 @given(
     seed=st.integers(0, 2**31 - 1),
     m=st.integers(2, 12),
@@ -158,7 +158,9 @@ def test_property_random_layouts(orc, seed, m, na, cuts):
     srt = np.sort(D, axis=1)
     with np.errstate(invalid="ignore"):
         clear = (srt[:, 1] - srt[:, 0] > 1e-9) if D.shape[1] > 1 else np.ones(len(P), bool)
+    clear &= np.isfinite(Ps)
     np.testing.assert_array_equal(I[clear], Is[clear])
+    assert np.all(I[np.isinf(Ps)] == -1)
     assert np.all((P[np.isfinite(P)] >= 0) & (P[np.isfinite(P)] <= 2 * math.sqrt(m) + 1e-12))
 
 
@@ -306,3 +308,47 @@ def test_invalid_arguments(orc):
         orc.ab_join(np.zeros(10), np.zeros(10), [0, 9], 3)  # does not end at n
     with pytest.raises(ValueError):
         orc.ab_join(np.zeros(2), np.zeros(10), [0, 10], 3)  # query shorter than m
+
+
+# ---------------------------------------------------------------- learning-phase primitives
+def test_self_join_matches_scipy_with_exclusion(orc):
+    """Alg. 1 line 3: intra-join with trivial-match exclusion |i - j| <= floor(m/2)."""
+    rng = np.random.default_rng(31)
+    for m in (4, 9, 32):
+        x = rng.standard_normal(400).cumsum()
+        P, I = orc.self_join(x, m)
+        Z = zscore(sliding_window_view(x, m), axis=1, ddof=0)
+        D = cdist(Z, Z)
+        W = len(D)
+        ii, jj = np.indices((W, W))
+        D[np.abs(ii - jj) <= m // 2] = np.inf
+        np.testing.assert_allclose(P, D.min(1), rtol=0, atol=1e-10)
+        np.testing.assert_array_equal(I, D.argmin(1))
+        assert np.all(np.abs(I - np.arange(W)) > m // 2)
+
+
+def test_self_join_exclusion_boundary(orc):
+    """A copy exactly floor(m/2)+1 away is found; one exactly floor(m/2) away is excluded."""
+    rng = np.random.default_rng(32)
+    m = 10
+    x = rng.standard_normal(200)
+    x[100:110] = x[50:60]  # window 100 copies window 50
+    P, I = orc.self_join(x, m)
+    assert P[50] < 1e-9 and I[50] == 100
+    y = rng.standard_normal(200)
+    y[55:65] = 3.0 * y[50:60] + 1.0  # 5 = floor(m/2) apart: a trivial match
+    P, I = orc.self_join(y, m)
+    assert I[50] != 55 and P[50] > 1e-3
+
+
+def test_dist_profile_matches_scipy(orc):
+    """Def. 4 distance profile of one query window against every window of x."""
+    rng = np.random.default_rng(33)
+    m = 24
+    x = rng.standard_normal(500).cumsum()
+    w = x[123:123 + m].copy()
+    S = orc.dist_profile(x, m, w)
+    Z = zscore(sliding_window_view(x, m), axis=1, ddof=0)
+    zw = zscore(w, ddof=0)
+    np.testing.assert_allclose(S, np.sqrt(((Z - zw) ** 2).sum(1)), rtol=0, atol=1e-10)
+    assert S[123] < 1e-12

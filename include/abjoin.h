@@ -65,10 +65,15 @@ typedef enum {
     ABJ_TIER_FP16 = 2  /* FP16 MFMA on centred, scaled windows + FP64 re-check of top-K */
 } abj_tier;
 
+/* opts.flags bits */
+#define ABJ_FLAG_NO_REFINE 1 /* precision tiers: skip the FP64 re-check and report the distance implied by the
+                                best 16-bit score (to measure the tier's error before refinement) */
+
 typedef struct {
     int32_t tier;     /* abj_tier */
-    int32_t refine_k; /* precision tiers: candidates re-checked per row, 1..8 (0 = 4) */
-    int32_t flags;    /* reserved, must be 0 */
+    int32_t refine_k; /* precision tiers: candidates kept per row and re-checked in FP64, 1..8 (0 = 4);
+                         rounded up to 1, 2, 4 or 8 */
+    int32_t flags;    /* ABJ_FLAG_* bits; 0 for default behaviour */
     int32_t reserved; /* must be 0 */
 } abj_opts;
 
@@ -104,10 +109,14 @@ int abj_window_stats(const double* x, int64_t n, int32_t m, double* mu, double* 
  *   seg_bounds  host, n_seg+1 int64 offsets (see conventions)
  *   P_AB    device, n_query-m+1 floats (out)  I_AB  device, n_query-m+1 int64 (out)
  *   opts    NULL = FP32 tier
- * Errors: ABJ_EINVAL if m < 2, n_query < m, n_dict < 1, n_seg < 1, bad
- * seg_bounds, an unknown tier, refine_k outside 0..8, nonzero reserved
- * fields, or a NULL / non-device pointer; ABJ_ENOMEM / ABJ_EHIP from the
- * runtime.  Workspace is taken from the stream-ordered allocator on
+ * FP32 tier: m <= 4096.  BF16 / FP16 tiers (the paper's join with 16-bit
+ * window products, a speed/accuracy option of this library): m <= 256; every
+ * row keeps its best refine_k candidates by 16-bit score per dictionary chunk
+ * and returns the one closest in FP64.
+ * Errors: ABJ_EINVAL if m < 2 (or above the tier's limit), n_query < m,
+ * n_dict < 1, n_seg < 1, bad seg_bounds, an unknown tier, refine_k outside
+ * 0..8, unknown flag bits, nonzero reserved field, or a NULL / non-device
+ * pointer; ABJ_ENOMEM / ABJ_EHIP from the runtime.  Workspace is taken from the stream-ordered allocator on
  * hip_stream and returned to it before the call's work completes.
  */
 int ab_join(const double* query, int64_t n_query, const double* dict, int64_t n_dict, const int64_t* seg_bounds,

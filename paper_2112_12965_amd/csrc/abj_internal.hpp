@@ -101,6 +101,22 @@ int finalize_launch(const SeriesDev& A, const SeriesDev& B, const unsigned long 
 
 int fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t stream);
 
+// Launch plan of the BF16/FP16 tier.
+struct MfmaPlan {
+    int tier = 0;
+    int KS = 0;                 // 16-wide k steps (m padded with zeros)
+    int K = 0;                  // candidates kept per row and chunk
+    int64_t nqblk = 0, ndblk = 0;  // 32-window blocks of query / dictionary
+    int64_t npanels = 0;        // query panels (one workgroup each per chunk)
+    int64_t blk_per_chunk = 0, nchunks = 0;  // dictionary split of the sweep
+};
+int mfma_plan(int64_t WA, int64_t WB, int32_t m, int tier, int refine_k, MfmaPlan* p);
+size_t mfma_scratch_bytes(const MfmaPlan& p);
+// Operands, matrix-core sweep, FP64 re-check of all candidates (or, with
+// refine = 0, the distance implied by the best 16-bit score), conventions.
+int join_mfma_run(const SeriesDev& A, const SeriesDev& B, const MfmaPlan& p, int refine, float* P, int64_t* I,
+                  Arena& ar, hipStream_t stream);
+
 int ensure_device();
 
 // Benchmark timing hooks (no-ops unless abj_profile_enable(1) was called):

@@ -223,10 +223,11 @@ extern "C" int ab_join(const double* query, int64_t n_query, const double* dict,
     // ---- validation: nothing is enqueued or written before this passes ----
     abj_opts o = {ABJ_TIER_FP32, 0, 0, 0};
     if (opts) o = *opts;
-    if (o.tier != ABJ_TIER_FP32)
-        return set_error(ABJ_EINVAL, "tier %d is not available", o.tier);
+    if (o.tier != ABJ_TIER_FP32 && o.tier != ABJ_TIER_BF16 && o.tier != ABJ_TIER_FP16)
+        return set_error(ABJ_EINVAL, "unknown tier %d", o.tier);
     if (o.refine_k < 0 || o.refine_k > 8) return set_error(ABJ_EINVAL, "refine_k must be in 0..8");
-    if (o.flags != 0 || o.reserved != 0) return set_error(ABJ_EINVAL, "opts.flags and opts.reserved must be 0");
+    if ((o.flags & ~ABJ_FLAG_NO_REFINE) != 0 || o.reserved != 0)
+        return set_error(ABJ_EINVAL, "unknown opts.flags bits or nonzero opts.reserved");
     if (m < 2 || m > kMaxM) return set_error(ABJ_EINVAL, "m must be in [2, %d] (got %d)", kMaxM, m);
     if (n_query < m || n_query > kMaxN)
         return set_error(ABJ_EINVAL, "n_query must be in [m, 2^31-1] (got %lld)", (long long)n_query);
@@ -239,6 +240,8 @@ extern "C" int ab_join(const double* query, int64_t n_query, const double* dict,
     ABJ_TRY(check_dev_buf(dict, sizeof(double) * (size_t)n_dict, "dict"));
     ABJ_TRY(check_dev_buf(P_AB, sizeof(float) * (size_t)WA, "P_AB"));
     ABJ_TRY(check_dev_buf(I_AB, sizeof(int64_t) * (size_t)WA, "I_AB"));
+    MfmaPlan plan;
+    if (o.tier != ABJ_TIER_FP32) ABJ_TRY(mfma_plan(WA, WB, m, o.tier, o.refine_k, &plan));
     ABJ_TRY(ensure_device());
 
     hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
@@ -247,6 +250,7 @@ extern "C" int ab_join(const double* query, int64_t n_query, const double* dict,
     ar.reserve(stats_scratch_bytes(n_dict, WB));
     ar.reserve(sizeof(unsigned long long) * (size_t)WA);
     ar.reserve(sizeof(int64_t) * (size_t)(n_seg + 1));
+    if (o.tier != ABJ_TIER_FP32) ar.reserve(mfma_scratch_bytes(plan));
     ABJ_TRY(ar.commit());
     SeriesDev A, B;
     stats_carve(ar, n_query, m, &A);
@@ -260,6 +264,8 @@ extern "C" int ab_join(const double* query, int64_t n_query, const double* dict,
     ABJ_HIP(hipMemcpyAsync(dbounds, seg_bounds, sizeof(int64_t) * (size_t)(n_seg + 1), hipMemcpyHostToDevice, stream));
     ABJ_TRY(stats_compute(query, &A, nullptr, 0, ar, stream));
     ABJ_TRY(stats_compute(dict, &B, dbounds, n_seg, ar, stream));
+    if (o.tier != ABJ_TIER_FP32)
+        return join_mfma_run(A, B, plan, !(o.flags & ABJ_FLAG_NO_REFINE), P_AB, I_AB, ar, stream);
     ABJ_TRY(fill_u64(keys, WA, 0ull, stream));
     ABJ_TRY(join_fp32_launch(A, B, keys, stream));
     return finalize_launch(A, B, keys, P_AB, I_AB, stream);

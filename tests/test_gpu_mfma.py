@@ -1,0 +1,146 @@
+"""GPU parity of the BF16 / FP16 precision tiers against the FP64 oracle.
+
+After the FP64 re-check of the top-K candidates the tiers are held to the
+FP32 tier's bar: |P - P_oracle| <= 1e-3, I equal where the oracle's
+best-to-second gap exceeds 1e-3, every returned neighbour within 1e-3 of the
+best.
+
+Before refinement (ABJ_FLAG_NO_REFINE) the tier reports the distance implied by
+its best 16-bit score.  With unit-norm windows rounded to a format of unit
+roundoff u, each product carries relative error <= 2u + u^2 and sum |za zb| <= 1,
+so the score error is |drho| <= 2u + u^2 + m 2^-24 (FP32 accumulation); the
+winner's score is then within that of the true best, so
+|P_hat^2 - P^2| <= 2 m |drho| and |P_hat - P| <= 2 m |drho| / (P_hat + P).
+The tests assert this bound and print the measured error.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import _parity
+from paper_2112_12965_amd import abjoin, synth
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-3
+UNIT_ROUNDOFF = {"bf16": 2.0 ** -9, "fp16": 2.0 ** -11}
+TIERS = ["bf16", "fp16"]
+
+
+def unrefined_bound(tier, m, P_hat, P):
+    u = UNIT_ROUNDOFF[tier]
+    drho = 2 * u + u * u + m * 2.0 ** -24
+    return 2 * m * drho / np.maximum(P_hat + P, np.sqrt(2 * m * drho)) + 1e-6
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def run(q, d, bounds, m, tier, refine=True, refine_k=0):
+    qd, dd = dev(q), dev(d)
+    W = len(q) - m + 1
+    P = torch.empty(W, dtype=torch.float32, device="cuda")
+    I = torch.empty(W, dtype=torch.int64, device="cuda")
+    b = np.ascontiguousarray(bounds, dtype=np.int64)
+    o = abjoin.abj_opts(abjoin.TIERS[tier], refine_k, 0 if refine else 1, 0)
+    rc = abjoin.lib().ab_join(qd.data_ptr(), len(q), dd.data_ptr(), len(d),
+                              b.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(b) - 1, m, P.data_ptr(),
+                              I.data_ptr(), ctypes.byref(o), None)
+    assert rc == 0, abjoin.last_error()
+    torch.cuda.synchronize()
+    return P.cpu().numpy().astype(np.float64), I.cpu().numpy()
+
+
+def check(orc, q, d, bounds, m, tier, rows=None):
+    print(f"[case] n_q={len(q)} n_d={len(d)} segs={len(bounds) - 1} m={m} tier={tier}", flush=True)
+    P, I = run(q, d, bounds, m, tier)
+    Pu, Iu = run(q, d, bounds, m, tier, refine=False)
+    Po, Io, P2o = orc.ab_join(q, d, bounds, m, rows=rows, second=True)
+    sel = slice(None) if rows is None else rows
+    st = _parity.compare(P[sel], I[sel], Po, Io, P2o, TOL, orc, q, d, m, rows=rows)
+    fin = np.isfinite(Po)
+    eu = np.abs(Pu[sel][fin] - Po[fin])
+    st["unrefined_max_abs"] = float(eu.max()) if eu.size else 0.0
+    st["unrefined_mean_abs"] = float(eu.mean()) if eu.size else 0.0
+    print(tier, st, flush=True)
+    bound = unrefined_bound(tier, m, Pu[sel][fin], Po[fin])
+    worst = np.flatnonzero(eu > bound)
+    assert worst.size == 0, (st, eu[worst[:5]], bound[worst[:5]])
+    return st
+
+
+@pytest.mark.parametrize("tier", TIERS)
+def test_small_random_walk_m100(orc, tier):
+    w = synth.WORKLOADS["rw2k_m100"]()
+    check(orc, w["query"], w["dict"], w["bounds"], w["m"], tier)
+
+
+@pytest.mark.parametrize("tier", TIERS)
+@pytest.mark.parametrize("m", [16, 64, 128, 200, 256])
+def test_multi_block_ragged_segments(orc, tier, m):
+    rng = np.random.default_rng(2000 + m)
+    q = synth.ecg_like(5003, rng, n_anomalies=2)
+    d = synth.ecg_like(4001, rng)
+    bounds = [0, 1500, 1500 + m - 1, 2850, 4001]
+    check(orc, q, d, bounds, m, tier)
+
+
+@pytest.mark.parametrize("tier", TIERS)
+def test_planted_copies(orc, tier):
+    rng = np.random.default_rng(6)
+    m = 128
+    d = synth.random_walk(6000, rng)
+    q = synth.random_walk(4000, rng)
+    q[100:100 + m] = 2.0 * d[3333:3333 + m] + 11.0
+    P, I = run(q, d, [0, len(d)], m, tier)
+    assert P[100] < 1e-3 and I[100] == 3333
+    check(orc, q, d, [0, len(d)], m, tier)
+
+
+@pytest.mark.parametrize("tier", TIERS)
+def test_flat_nonfinite_degenerate(orc, tier):
+    m = 32
+    rng = np.random.default_rng(29)
+    q = rng.standard_normal(3000)
+    q[10:60] = 2.5
+    q[45] = np.nan
+    d = rng.standard_normal(2500)
+    d[500:560] = -1.0
+    d[5] = np.inf
+    check(orc, q, d, [0, 1200, 2500], m, tier)
+    P, I = run(q[:100], rng.standard_normal(60), [0, 20, 40, 60], m, tier)  # no segment holds a window
+    assert np.all(np.isnan(P) | np.isinf(P)) and np.all(I == -1)
+
+
+def test_refine_k_values(orc):
+    w = synth.WORKLOADS["rw2k_m100"]()
+    for k in (1, 2, 3, 8):
+        P, I = run(w["query"], w["dict"], w["bounds"], w["m"], "fp16", refine_k=k)
+        Po, Io = orc.ab_join(w["query"], w["dict"], w["bounds"], w["m"])
+        assert np.abs(P - Po).max() <= 2e-2, k
+
+
+def test_m_above_256_rejected():
+    q = dev(np.random.default_rng(1).standard_normal(1000))
+    with pytest.raises(abjoin.AbjError) as e:
+        abjoin.ab_join(q, q, [0, 1000], 257, tier="bf16")
+    assert e.value.code == abjoin.ABJ_EINVAL
+
+
+@pytest.mark.parametrize("tier", TIERS)
+def test_dictionary_workload_sampled_rows(orc, tier):
+    w = synth.WORKLOADS["ecg131k_dict16x2000_m256"]()
+    W = len(w["query"]) - w["m"] + 1
+    rows = np.unique(np.concatenate([np.random.default_rng(3).choice(W, 256, replace=False),
+                                     np.clip(w["anomalies"], 0, W - 1), [0, W - 1]]))
+    check(orc, w["query"], w["dict"], w["bounds"], w["m"], tier, rows=rows)
+
+
+@pytest.mark.parametrize("tier", TIERS)
+def test_large_random_walk_sampled_rows(orc, tier):
+    w = synth.WORKLOADS["rw1m_m128"]()
+    W = len(w["query"]) - w["m"] + 1
+    rows = np.unique(np.concatenate([np.random.default_rng(4).choice(W, 64, replace=False), [0, W - 1]]))
+    check(orc, w["query"], w["dict"], w["bounds"], w["m"], tier, rows=rows)

@@ -91,9 +91,32 @@ void stats_carve(Arena& a, int64_t n, int32_t m, SeriesDev* s);
 int stats_compute(const double* x, SeriesDev* s, const int64_t* seg_bounds_dev, int32_t n_seg, Arena& a,
                   hipStream_t stream);
 
-// FP32 diagonal join of all valid query windows against all valid reference
-// windows; writes one packed (score, index) key per query row.
-int join_fp32_launch(const SeriesDev& A, const SeriesDev& B, unsigned long long* keys, hipStream_t stream);
+// One query series (a "slot") of an FP32 batch launch: its statistics, the
+// reference statistics for the same m, its key array, and its tiles
+// (nbands x nchunks, numbered from tile0 in the launch's tile list).
+struct Fp32Slot {
+    const double* axc;
+    const double* amu;
+    const float2* adfdg;
+    int64_t WA;
+    const double* bxc;
+    const double* bmu;
+    const float4* bcol;
+    int64_t WB;
+    unsigned long long* keys;
+    int64_t tile0;
+    int64_t nbands, nchunks, tc;
+    int64_t pairs;  // valid pairs (for timing records)
+    int32_t m;
+    int32_t pad;
+};
+void fp32_slot(const SeriesDev& A, const SeriesDev& B, unsigned long long* keys, int64_t tile0, Fp32Slot* sl);
+int64_t fp32_slot_tiles(const Fp32Slot& sl);
+size_t fp32_lds_bytes(int max_m);
+// FP32 diagonal join of every tile of every slot (persistent workgroups, one
+// atomic tile counter); writes one packed (score, index) key per query row.
+int join_fp32_batch(const Fp32Slot* slots_dev, int nslots, int64_t ntiles, int max_m, int64_t pairs,
+                    unsigned long long* counter_dev, hipStream_t stream);
 
 // Turns packed keys into P (FP64 re-check, flat conventions) and I.
 int finalize_launch(const SeriesDev& A, const SeriesDev& B, const unsigned long long* keys, float* P, int64_t* I,

@@ -250,6 +250,8 @@ extern "C" int ab_join(const double* query, int64_t n_query, const double* dict,
     ar.reserve(stats_scratch_bytes(n_dict, WB));
     ar.reserve(sizeof(unsigned long long) * (size_t)WA);
     ar.reserve(sizeof(int64_t) * (size_t)(n_seg + 1));
+    ar.reserve(sizeof(Fp32Slot));
+    ar.reserve(sizeof(unsigned long long));
     if (o.tier != ABJ_TIER_FP32) ar.reserve(mfma_scratch_bytes(plan));
     ABJ_TRY(ar.commit());
     SeriesDev A, B;
@@ -267,6 +269,11 @@ extern "C" int ab_join(const double* query, int64_t n_query, const double* dict,
     if (o.tier != ABJ_TIER_FP32)
         return join_mfma_run(A, B, plan, !(o.flags & ABJ_FLAG_NO_REFINE), P_AB, I_AB, ar, stream);
     ABJ_TRY(fill_u64(keys, WA, 0ull, stream));
-    ABJ_TRY(join_fp32_launch(A, B, keys, stream));
+    Fp32Slot sl;
+    fp32_slot(A, B, keys, 0, &sl);
+    Fp32Slot* dslot = ar.take<Fp32Slot>(1);
+    unsigned long long* counter = ar.take<unsigned long long>(1);
+    ABJ_HIP(hipMemcpyAsync(dslot, &sl, sizeof(sl), hipMemcpyHostToDevice, stream));
+    ABJ_TRY(join_fp32_batch(dslot, 1, fp32_slot_tiles(sl), m, sl.pairs, counter, stream));
     return finalize_launch(A, B, keys, P_AB, I_AB, stream);
 }

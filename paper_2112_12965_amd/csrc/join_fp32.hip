@@ -42,9 +42,8 @@ constexpr int kG = 8;                   // width of the FP64 edge dot-product gr
 
 // acc[g] = sum_{k<m} w[k] * x[base + g + k] for g < G.  x is read through a
 // G-entry register window that slides by one sample per k (one load per G FMAs).
-template <int G>
-__device__ inline void sliding_dots(const double* __restrict__ x, int64_t base, const double* w, int m,
-                                    double (&acc)[G])
+template <int G, typename Ptr>
+__device__ inline void sliding_dots(Ptr __restrict__ x, int64_t base, const double* w, int m, double (&acc)[G])
 {
     double win[G];
 #pragma unroll
@@ -77,6 +76,16 @@ __device__ inline double wave_sum(double v)
     return v;
 }
 
+// Column records are read-only for a whole launch: reading them through the
+// constant address space lets the wave-uniform loads of the sweep be scalar.
+typedef float vf4 __attribute__((ext_vector_type(4)));  // same layout as float4
+typedef float vf2 __attribute__((ext_vector_type(2)));  // same layout as float2
+typedef const __attribute__((address_space(4))) vf4* ColPtr;
+// The slot's arrays live in global memory; saying so keeps their loads global
+// (not flat) although the pointers come from a descriptor in memory.
+typedef const __attribute__((address_space(1))) double* GDbl;
+typedef const __attribute__((address_space(1))) vf2* GVf2;
+
 __host__ __device__ inline size_t edge_offset(int m) { return ((size_t)m * sizeof(double) + 15) & ~size_t(15); }
 
 __device__ inline unsigned long long pack_key(float s, int j)
@@ -90,25 +99,25 @@ __device__ inline unsigned long long pack_key(float s, int j)
 // register slot (r - U) mod kR; the step writes new row r over old row r-1
 // (in place, no register moves), so on exit row r lives in slot (r - U - 1).
 template <int U, bool kGuard>
-__device__ __forceinline__ bool sweep_step(int64_t j, int64_t jend, const float4* __restrict__ bcol, float e,
+__device__ __forceinline__ bool sweep_step(int64_t j, int64_t jend, ColPtr __restrict__ bcol, float e,
                                            float (&S)[kR], const float (&pf)[kR], const float (&pg)[kR],
-                                           float (&best)[kR], int (&bidx)[kR], float4& prev)
+                                           float (&best)[kR], int (&bidx)[kR], vf4& prev)
 {
     if (kGuard && j >= jend) return false;
-    const float4 cur = bcol[j];
+    const vf4 cur = bcol[j];
     // lanes 1..63 receive the last row of the lane below; lane 0 keeps the edge
     const float t = __int_as_float(__builtin_amdgcn_update_dpp(
         __float_as_int(e), __float_as_int(S[(kR - 1 - U) & (kR - 1)]), kDppWaveShr1, 0xf, 0xf, false));
 #pragma unroll
     for (int r = kR - 1; r >= 1; --r) {
         float& c = S[(r - 1 - U) & (kR - 1)];
-        c = fmaf(pg[r], prev.x, fmaf(pf[r], prev.y, c));
+        c = fmaf(pg[r], prev[0], fmaf(pf[r], prev[1], c));
     }
-    S[(kR - 1 - U) & (kR - 1)] = fmaf(pg[0], prev.x, fmaf(pf[0], prev.y, t));
-    if (cur.z != 0.f) {
+    S[(kR - 1 - U) & (kR - 1)] = fmaf(pg[0], prev[0], fmaf(pf[0], prev[1], t));
+    if (cur[2] != 0.f) {
 #pragma unroll
         for (int r = 0; r < kR; ++r) {
-            const float sc = S[(r - 1 - U) & (kR - 1)] * cur.z;
+            const float sc = S[(r - 1 - U) & (kR - 1)] * cur[2];
             const bool up = sc > best[r];
             // improvements are rare after the first columns: branch only when
             // some lane improves this row
@@ -128,10 +137,10 @@ __device__ __forceinline__ bool sweep_step(int64_t j, int64_t jend, const float4
 // kR consecutive steps starting at column jb; edge values e[0..kR) belong to
 // columns jb .. jb+kR-1.
 template <bool kGuard>
-__device__ __forceinline__ void sweep_block(int64_t jb, int64_t jend, const float4* __restrict__ bcol,
+__device__ __forceinline__ void sweep_block(int64_t jb, int64_t jend, ColPtr __restrict__ bcol,
                                             const float (&e)[kR], float (&S)[kR], const float (&pf)[kR],
                                             const float (&pg)[kR], float (&best)[kR], int (&bidx)[kR],
-                                            float4& prev)
+                                            vf4& prev)
 {
 #define ABJ_STEP(u) \
     if (!sweep_step<u, kGuard>(jb + u, jend, bcol, e[u], S, pf, pg, best, bidx, prev)) return;
@@ -140,19 +149,25 @@ __device__ __forceinline__ void sweep_block(int64_t jb, int64_t jend, const floa
 #undef ABJ_STEP
 }
 
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void k_join_fp32(
-    const double* __restrict__ axc, const double* __restrict__ amu, const float2* __restrict__ adfdg, int64_t WA,
-    const double* __restrict__ bxc, const double* __restrict__ bmu, const float4* __restrict__ bcol, int64_t WB,
-    int m, int nchunks, int tc, unsigned long long* __restrict__ keys)
+// One tile: rows band * 1024 .. +1023 of slot `sl`, columns chunk * tc .. +tc-1.
+__device__ __forceinline__ void join_tile(const Fp32Slot& sl, int64_t band, int64_t chunk, double* lds)
 {
-    extern __shared__ double lds[];
+    GDbl __restrict__ axc = (GDbl)sl.axc;
+    GDbl __restrict__ amu = (GDbl)sl.amu;
+    GVf2 __restrict__ adfdg = (GVf2)sl.adfdg;
+    GDbl __restrict__ bxc = (GDbl)sl.bxc;
+    GDbl __restrict__ bmu = (GDbl)sl.bmu;
+    ColPtr __restrict__ bcol = (ColPtr)sl.bcol;
+    unsigned long long* __restrict__ keys = sl.keys;
+    const int64_t WA = sl.WA, WB = sl.WB;
+    const int m = sl.m;
+    const int64_t tc = sl.tc;
+
     double* wv = lds;                                  // m doubles: one centred window
     // kTC + kR floats, 16-byte aligned: edge[t] = cov(i0, j0 + 1 + t)
     float* edge = reinterpret_cast<float*>(reinterpret_cast<char*>(lds) + edge_offset(m));
 
     const int lane = threadIdx.x;
-    const int64_t band = blockIdx.x / nchunks;
-    const int64_t chunk = blockIdx.x - band * nchunks;
     const int64_t i0 = band * kBandRows;
     const int64_t j0 = chunk * tc;  // tc <= kTC columns per tile, chosen by the host to balance tiles
     const int64_t jend = j0 + tc < WB ? j0 + tc : WB;
@@ -219,15 +234,15 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void
         const int64_t i = ibase + r;
         // terms of the step from row i-1 into row i; zero for the tile's top
         // row (lane 0, r 0) so that lane 0 takes the top edge unchanged
-        float2 t = make_float2(0.f, 0.f);
+        vf2 t = {0.f, 0.f};
         if (i > i0 && i - 1 < WA - 1) t = adfdg[i - 1];
-        pf[r] = t.x;
-        pg[r] = t.y;
+        pf[r] = t[0];
+        pg[r] = t[1];
         best[r] = -INFINITY;
         bidx[r] = -1;
     }
     {
-        const float inv = bcol[j0].z;
+        const float inv = bcol[j0][2];
         if (inv != 0.f) {
 #pragma unroll
             for (int r = 0; r < kR; ++r) {
@@ -236,7 +251,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void
             }
         }
     }
-    float4 prev = bcol[j0];
+    vf4 prev = bcol[j0];
     const int64_t nfull = (jend - j0 - 1) / kR;  // full 16-column blocks after column j0
     for (int64_t b = 0; b < nfull; ++b) {
         const int64_t jb = j0 + 1 + b * kR;
@@ -268,26 +283,82 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void
     }
 }
 
+// Persistent batch kernel: every workgroup (one wave) takes tiles from the
+// launch's list through one atomic counter until the list is exhausted (the
+// list is finite, so every wave reaches the exit).  Tiles of different slots
+// (requests) with different lengths and window lengths share the launch.
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void k_join_fp32_batch(
+    const Fp32Slot* __restrict__ slots, int nslots, int64_t ntiles, unsigned long long* __restrict__ counter)
+{
+    extern __shared__ double lds[];
+    for (;;) {
+        unsigned long long t = 0;
+        if (threadIdx.x == 0) t = atomicAdd(counter, 1ull);
+        // wave-uniform tile index in scalar registers, so that everything derived
+        // from it (slot, pointers, column loop) stays scalar
+        t = __shfl(t, 0, kWave);
+        const unsigned tlo = __builtin_amdgcn_readfirstlane((unsigned)t);
+        const unsigned thi = __builtin_amdgcn_readfirstlane((unsigned)(t >> 32));
+        t = ((unsigned long long)thi << 32) | tlo;
+        if (t >= (unsigned long long)ntiles) break;
+        // slot holding tile t: the last slot whose first tile is <= t
+        int lo = 0, hi = nslots;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if ((unsigned long long)slots[mid].tile0 <= t) lo = mid;
+            else hi = mid;
+        }
+        const Fp32Slot sl = slots[lo];
+        const int64_t lt = (int64_t)t - sl.tile0;
+        const int64_t band = lt / sl.nchunks;
+        join_tile(sl, band, lt - band * sl.nchunks, lds);
+        __syncthreads();  // the next tile reuses the LDS buffers
+    }
+}
+
 }  // namespace
 
-int join_fp32_launch(const SeriesDev& A, const SeriesDev& B, unsigned long long* keys, hipStream_t stream)
+void fp32_slot(const SeriesDev& A, const SeriesDev& B, unsigned long long* keys, int64_t tile0, Fp32Slot* sl)
 {
-    if (A.W <= 0 || B.W <= 0) return ABJ_OK;
-    const int64_t nbands = (A.W + kBandRows - 1) / kBandRows;
-    const int64_t nchunks = (B.W + kTC - 1) / kTC;
+    sl->axc = A.xc;
+    sl->amu = A.mu;
+    sl->adfdg = A.dfdg;
+    sl->WA = A.W;
+    sl->bxc = B.xc;
+    sl->bmu = B.mu;
+    sl->bcol = B.col;
+    sl->WB = B.W;
+    sl->m = A.m;
+    sl->keys = keys;
+    sl->tile0 = tile0;
+    sl->nbands = A.W > 0 ? (A.W + kBandRows - 1) / kBandRows : 0;
+    int64_t nchunks = B.W > 0 ? (B.W + kTC - 1) / kTC : 0;
     // equal chunk widths (multiple of 16) so that no tile is a sliver
-    int64_t tc = (B.W + nchunks - 1) / nchunks;
+    int64_t tc = nchunks > 0 ? (B.W + nchunks - 1) / nchunks : kTC;
     tc = (tc + kR - 1) / kR * kR;
     if (tc > kTC) tc = kTC;
-    const int64_t blocks = nbands * nchunks;
-    if (blocks > 0x7fffffffLL) return set_error(ABJ_EINVAL, "join too large for one launch (%lld tiles)", (long long)blocks);
-    const size_t lds = edge_offset((int)A.m) + sizeof(float) * (kTC + kR);
+    sl->nchunks = nchunks;
+    sl->tc = tc;
+    sl->pairs = A.W * B.nvalid;
+}
+
+int64_t fp32_slot_tiles(const Fp32Slot& sl) { return sl.nbands * sl.nchunks; }
+
+size_t fp32_lds_bytes(int max_m) { return edge_offset(max_m) + sizeof(float) * (kTC + kR); }
+
+int join_fp32_batch(const Fp32Slot* slots_dev, int nslots, int64_t ntiles, int max_m, int64_t pairs,
+                    unsigned long long* counter_dev, hipStream_t stream)
+{
+    if (ntiles <= 0) return ABJ_OK;
+    ABJ_TRY(fill_u64(counter_dev, 1, 0ull, stream));
+    // enough one-wave workgroups to fill every SIMD four deep, never more than tiles
+    const int64_t grid = ntiles < 4096 ? ntiles : 4096;
     ProfMark mark;
     ABJ_TRY(prof_begin(&mark, stream));
-    hipLaunchKernelGGL(k_join_fp32, dim3((unsigned)blocks), dim3(kWave), lds, stream, A.xc, A.mu, A.dfdg, A.W, B.xc,
-                       B.mu, B.col, B.W, (int)A.m, (int)nchunks, (int)tc, keys);
+    hipLaunchKernelGGL(k_join_fp32_batch, dim3((unsigned)grid), dim3(kWave), fp32_lds_bytes(max_m), stream,
+                       slots_dev, nslots, ntiles, counter_dev);
     ABJ_HIP(hipGetLastError());
-    return prof_end(&mark, stream, A.W * B.nvalid);
+    return prof_end(&mark, stream, pairs);
 }
 
 }  // namespace abj

@@ -122,6 +122,94 @@ int abj_window_stats(const double* x, int64_t n, int32_t m, double* mu, double* 
 int ab_join(const double* query, int64_t n_query, const double* dict, int64_t n_dict, const int64_t* seg_bounds,
             int32_t n_seg, int32_t m, float* P_AB, int64_t* I_AB, const abj_opts* opts, void* hip_stream);
 
+/* ------------------------------------------------------------------------
+ * Resident dictionary: the learned dictionary of the inference phase (Alg. 2
+ * joins every incoming series against the same D_B) kept in library-owned
+ * device memory with its per-window statistics precomputed for each window
+ * length in ms[].
+ * ---------------------------------------------------------------------- */
+typedef struct abj_dict abj_dict;
+
+/*
+ * dict: host or device pointer to n_dict doubles (copied; the caller keeps
+ * ownership).  seg_bounds: host, n_seg+1 offsets.  ms: host, n_ms window
+ * lengths (each 2..4096, n_ms 1..16).  Errors: ABJ_EINVAL on bad sizes, bounds
+ * or pointers; ABJ_ENOMEM / ABJ_EHIP from the runtime.
+ */
+int abj_dict_create(const double* dict, int64_t n_dict, const int64_t* seg_bounds, int32_t n_seg, const int32_t* ms,
+                    int32_t n_ms, abj_dict** out);
+int abj_dict_free(abj_dict* d);
+
+/* ab_join against a resident dictionary (m must be one of its ms).  Same
+ * conventions, outputs and errors as ab_join; query, P_AB, I_AB are device
+ * pointers. */
+int ab_join_dict(const abj_dict* d, const double* query, int64_t n_query, int32_t m, float* P_AB, int64_t* I_AB,
+                 const abj_opts* opts, void* hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of joins against a resident dictionary.
+ * A scheduler thread admits queued requests while a slot and memory are
+ * free, launches every admitted request's tiles together in one persistent
+ * FP32 batch kernel (two launches in flight on two streams, so requests that
+ * arrive while one batch runs join the next), and completes each request when
+ * its batch finishes.  The BF16/FP16 tiers run admitted requests as separate
+ * launches on the same two streams.
+ * ---------------------------------------------------------------------- */
+typedef struct abj_server abj_server;
+
+typedef struct {
+    int32_t tier;            /* abj_tier for every request */
+    int32_t max_slots;       /* requests admitted at once (>= 1) */
+    int64_t mem_budget;      /* device bytes for admitted requests (> 0) */
+    int32_t backend;         /* 0 = GPU; 1 = host simulation (no GPU calls; dict must be NULL) */
+    int32_t sim_n_ms;        /* simulation only: accepted window lengths ... */
+    int32_t sim_ms[8];
+    int64_t sim_dict_windows;   /* ... dictionary window count used for pair counts */
+    double sim_pairs_per_s;     /* ... simulated execution rate */
+} abj_server_opts;
+
+typedef struct {
+    double t_arrive; /* seconds since server creation: submit */
+    double t_admit;  /* admitted (slot + memory granted) */
+    double t_start;  /* its batch was launched */
+    double t_done;   /* results on the host */
+    int64_t pairs;   /* valid pairs of the request */
+    int32_t status;  /* ABJ_OK, ABJ_ECANCELED, or an error code */
+    int32_t batch;   /* launch the request ran in */
+} abj_req_stats;
+
+typedef struct {
+    int64_t submitted, completed, canceled, rejected, batches;
+    int64_t pairs;               /* valid pairs of completed requests */
+    double busy_s;               /* first launch to last completion */
+    double p50_s, p99_s, max_s;  /* latency t_done - t_arrive of completed requests */
+} abj_server_stats;
+
+/* Errors: ABJ_EINVAL on bad options (or a NULL dict with backend 0). */
+int abj_server_create(const abj_dict* d, const abj_server_opts* opts, abj_server** out);
+/* query_host: host pointer, copied before return.  Errors: ABJ_EINVAL if
+ * n_query < m or m is not a window length of the dictionary (the request is
+ * rejected; others are unaffected); ABJ_ENOMEM if the request alone exceeds
+ * the memory budget. */
+int abj_submit(abj_server* s, const double* query_host, int64_t n_query, int32_t m, uint64_t* req_id);
+/* Blocks until the request is done (ABJ_OK), canceled (ABJ_ECANCELED) or the
+ * timeout passes (ABJ_ETIMEOUT; timeout_ms < 0 waits forever).  ABJ_ENOTFOUND
+ * for unknown ids. */
+int abj_wait(abj_server* s, uint64_t req_id, int32_t timeout_ms);
+/* Copies a finished request's results (n_query-m+1 entries each; either may
+ * be NULL) and statistics, then forgets the request.  ABJ_EBUSY if it is not
+ * finished yet. */
+int abj_result(abj_server* s, uint64_t req_id, float* P_host, int64_t* I_host, abj_req_stats* st);
+/* Cancels a request that has not been launched yet (ABJ_OK); a launched
+ * request completes normally (ABJ_EBUSY). */
+int abj_cancel(abj_server* s, uint64_t req_id);
+/* Waits until no request is queued or running (ABJ_ETIMEOUT otherwise). */
+int abj_server_drain(abj_server* s, int32_t timeout_ms);
+int abj_server_stats_get(abj_server* s, abj_server_stats* out);
+/* Stops the scheduler after the running batches finish; queued requests are
+ * canceled.  Results not yet collected are discarded. */
+int abj_server_destroy(abj_server* s);
+
 /*
  * Benchmark timing.  While enabled (on != 0), every join records a HIP event
  * pair around its pair-loop kernel on the call's stream.  abj_profile_read

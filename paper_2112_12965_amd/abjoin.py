@@ -37,6 +37,25 @@ class abj_opts(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+class abj_server_opts(ctypes.Structure):
+    _fields_ = [("tier", ctypes.c_int32), ("max_slots", ctypes.c_int32), ("mem_budget", ctypes.c_int64),
+                ("backend", ctypes.c_int32), ("sim_n_ms", ctypes.c_int32), ("sim_ms", ctypes.c_int32 * 8),
+                ("sim_dict_windows", ctypes.c_int64), ("sim_pairs_per_s", ctypes.c_double)]
+
+
+class abj_req_stats(ctypes.Structure):
+    _fields_ = [("t_arrive", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_start", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("pairs", ctypes.c_int64), ("status", ctypes.c_int32),
+                ("batch", ctypes.c_int32)]
+
+
+class abj_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("canceled", ctypes.c_int64),
+                ("rejected", ctypes.c_int64), ("batches", ctypes.c_int64), ("pairs", ctypes.c_int64),
+                ("busy_s", ctypes.c_double), ("p50_s", ctypes.c_double), ("p99_s", ctypes.c_double),
+                ("max_s", ctypes.c_double)]
+
+
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
 _i32 = ctypes.c_int32
@@ -63,7 +82,23 @@ def lib():
         L.abj_window_stats.argtypes = [_vp, _i64, _i32, _vp, _vp, _vp, _vp]
         L.ab_join.argtypes = [_vp, _i64, _vp, _i64, ctypes.POINTER(_i64), _i32, _i32, _vp, _vp,
                               ctypes.POINTER(abj_opts), _vp]
-        for f in ("abj_init", "abj_window_stats", "ab_join"):
+        L.abj_profile_enable.argtypes = [ctypes.c_int]
+        L.abj_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
+        L.abj_dict_create.argtypes = [_vp, _i64, ctypes.POINTER(_i64), _i32, ctypes.POINTER(_i32), _i32,
+                                      ctypes.POINTER(_vp)]
+        L.abj_dict_free.argtypes = [_vp]
+        L.ab_join_dict.argtypes = [_vp, _vp, _i64, _i32, _vp, _vp, ctypes.POINTER(abj_opts), _vp]
+        L.abj_server_create.argtypes = [_vp, ctypes.POINTER(abj_server_opts), ctypes.POINTER(_vp)]
+        L.abj_submit.argtypes = [_vp, _vp, _i64, _i32, ctypes.POINTER(ctypes.c_uint64)]
+        L.abj_wait.argtypes = [_vp, ctypes.c_uint64, _i32]
+        L.abj_result.argtypes = [_vp, ctypes.c_uint64, _vp, _vp, ctypes.POINTER(abj_req_stats)]
+        L.abj_cancel.argtypes = [_vp, ctypes.c_uint64]
+        L.abj_server_drain.argtypes = [_vp, _i32]
+        L.abj_server_stats_get.argtypes = [_vp, ctypes.POINTER(abj_server_stats)]
+        L.abj_server_destroy.argtypes = [_vp]
+        for f in ("abj_init", "abj_window_stats", "ab_join", "abj_profile_enable", "abj_profile_read",
+                  "abj_dict_create", "abj_dict_free", "ab_join_dict", "abj_server_create", "abj_submit", "abj_wait",
+                  "abj_result", "abj_cancel", "abj_server_drain", "abj_server_stats_get", "abj_server_destroy"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -139,3 +174,126 @@ def window_stats(x, m: int, stream=None):
                                   sig.data_ptr() if W else None, fl.data_ptr() if W else None,
                                   _stream_ptr(stream)))
     return mu, sig, fl
+
+
+class Dictionary:
+    """A dictionary kept resident in device memory (library-owned), with window
+    statistics precomputed for every window length in ``ms``."""
+
+    def __init__(self, dictionary, seg_bounds, ms):
+        import torch
+
+        if isinstance(dictionary, torch.Tensor):
+            x = dictionary.detach().to(torch.float64).contiguous()
+            ptr, n, self._keep = x.data_ptr(), x.numel(), x
+        else:
+            x = np.ascontiguousarray(np.asarray(dictionary, dtype=np.float64))
+            ptr, n, self._keep = x.ctypes.data, len(x), x
+        b, bp, nseg = _bounds(seg_bounds)
+        m_arr = (ctypes.c_int32 * len(ms))(*[int(v) for v in ms])
+        h = ctypes.c_void_p()
+        _check(lib().abj_dict_create(ptr, n, bp, nseg, m_arr, len(ms), ctypes.byref(h)))
+        self.handle = h
+        self.ms = tuple(int(v) for v in ms)
+        self.n = n
+        self.bounds = b
+
+    def join(self, query, m, tier="fp32", refine_k=0, no_refine=False, out=None, stream=None):
+        import torch
+
+        q = _dev_f64(query, "query")
+        W = max(q.numel() - m + 1, 0)
+        if out is None:
+            P = torch.empty(W, dtype=torch.float32, device=q.device)
+            I = torch.empty(W, dtype=torch.int64, device=q.device)
+        else:
+            P, I = out
+        o = abj_opts(TIERS[tier], int(refine_k), 1 if no_refine else 0, 0)
+        _check(lib().ab_join_dict(self.handle, q.data_ptr(), q.numel(), int(m), P.data_ptr() if W else None,
+                                  I.data_ptr() if W else None, ctypes.byref(o), _stream_ptr(stream)))
+        return P, I
+
+    def close(self):
+        if self.handle:
+            lib().abj_dict_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching join server over a resident Dictionary.
+
+    ``backend="sim"`` runs the scheduler without any GPU call (for tests):
+    then ``dictionary`` is None and ``sim_ms`` / ``sim_dict_windows`` /
+    ``sim_pairs_per_s`` describe the simulated dictionary and speed.
+    """
+
+    def __init__(self, dictionary=None, tier="fp32", max_slots=64, mem_budget=8 << 30, backend="gpu",
+                 sim_ms=(64, 128, 256), sim_dict_windows=60000, sim_pairs_per_s=1e12):
+        o = abj_server_opts()
+        o.tier = TIERS[tier]
+        o.max_slots = int(max_slots)
+        o.mem_budget = int(mem_budget)
+        o.backend = {"gpu": 0, "sim": 1}[backend]
+        o.sim_n_ms = len(sim_ms)
+        for k, v in enumerate(sim_ms):
+            o.sim_ms[k] = int(v)
+        o.sim_dict_windows = int(sim_dict_windows)
+        o.sim_pairs_per_s = float(sim_pairs_per_s)
+        h = ctypes.c_void_p()
+        _check(lib().abj_server_create(dictionary.handle if dictionary is not None else None, ctypes.byref(o),
+                                       ctypes.byref(h)))
+        self.handle = h
+        self._dict = dictionary
+        self._lens = {}
+
+    def submit(self, query, m):
+        q = np.ascontiguousarray(np.asarray(query, dtype=np.float64))
+        rid = ctypes.c_uint64()
+        _check(lib().abj_submit(self.handle, q.ctypes.data, len(q), int(m), ctypes.byref(rid)))
+        self._lens[rid.value] = len(q) - int(m) + 1
+        return rid.value
+
+    def wait(self, rid, timeout_ms=-1):
+        """Status code: ABJ_OK, ABJ_ECANCELED, ABJ_ETIMEOUT, ..."""
+        return lib().abj_wait(self.handle, ctypes.c_uint64(rid), int(timeout_ms))
+
+    def result(self, rid):
+        """(P, I, stats) of a finished request (numpy arrays, dict)."""
+        W = self._lens[rid]
+        P = np.empty(W, dtype=np.float32)
+        I = np.empty(W, dtype=np.int64)
+        st = abj_req_stats()
+        rc = lib().abj_result(self.handle, ctypes.c_uint64(rid), P.ctypes.data, I.ctypes.data, ctypes.byref(st))
+        stats = {f: getattr(st, f) for f, _ in abj_req_stats._fields_}
+        if rc != ABJ_OK:
+            raise AbjError(rc, last_error())
+        del self._lens[rid]
+        return P, I, stats
+
+    def cancel(self, rid):
+        return lib().abj_cancel(self.handle, ctypes.c_uint64(rid))
+
+    def drain(self, timeout_ms=-1):
+        return lib().abj_server_drain(self.handle, int(timeout_ms))
+
+    def stats(self):
+        st = abj_server_stats()
+        _check(lib().abj_server_stats_get(self.handle, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in abj_server_stats._fields_}
+
+    def close(self):
+        if self.handle:
+            lib().abj_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

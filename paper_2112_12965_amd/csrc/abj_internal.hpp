@@ -58,6 +58,9 @@ struct SeriesDev {
 class Arena {
   public:
     explicit Arena(hipStream_t s) : stream_(s) {}
+    // Carves from caller-owned memory of `bytes` bytes (commit() is then a no-op
+    // and nothing is freed).
+    Arena(void* base, size_t bytes) : base_(static_cast<char*>(base)), need_(bytes), external_(true) {}
     ~Arena();
     void reserve(size_t bytes) { need_ += (bytes + 255) & ~size_t(255); }
     int commit();
@@ -73,9 +76,10 @@ class Arena {
 
   private:
     [[noreturn]] static void abort_overflow(size_t want, size_t have);
-    hipStream_t stream_;
+    hipStream_t stream_ = nullptr;
     char* base_ = nullptr;
     size_t need_ = 0, used_ = 0;
+    bool external_ = false;
 };
 
 // Bytes of scratch that stats_compute needs for a series of n samples.
@@ -141,6 +145,20 @@ int join_mfma_run(const SeriesDev& A, const SeriesDev& B, const MfmaPlan& p, int
                   Arena& ar, hipStream_t stream);
 
 int ensure_device();
+
+// Argument checks shared by the entry points (set the error text).
+int check_dev_buf(const void* p, size_t bytes, const char* name);
+int check_bounds(const int64_t* sb, int32_t n_seg, int64_t n_dict);
+int check_opts(const abj_opts* opts, abj_opts* out);
+constexpr int32_t kMaxM = 4096;
+constexpr int64_t kMaxN = (1LL << 31) - 1;
+
+// Device bytes that join_query needs for one query of n samples.
+size_t query_scratch_bytes(int64_t n, int32_t m, int64_t WB, const abj_opts& o, const MfmaPlan& plan);
+// Query-side join against reference statistics B: query statistics, pair loop
+// of the selected tier, row epilogue.  All scratch comes from `ar`.
+int join_query(const double* query, int64_t n, int32_t m, const SeriesDev& B, const abj_opts& o,
+               const MfmaPlan& plan, float* P, int64_t* I, Arena& ar, hipStream_t stream);
 
 // Benchmark timing hooks (no-ops unless abj_profile_enable(1) was called):
 // prof_begin records a start event on the stream, prof_end the stop event and

@@ -59,7 +59,7 @@ int set_error(int code, const char* fmt, ...)
 
 Arena::~Arena()
 {
-    if (base_) (void)hipFreeAsync(base_, stream_);
+    if (base_ && !external_) (void)hipFreeAsync(base_, stream_);
 }
 
 void Arena::abort_overflow(size_t want, size_t have)
@@ -70,7 +70,7 @@ void Arena::abort_overflow(size_t want, size_t have)
 
 int Arena::commit()
 {
-    if (need_ == 0) return ABJ_OK;
+    if (need_ == 0 || external_) return ABJ_OK;
     hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&base_), need_, stream_);
     if (e != hipSuccess) {
         base_ = nullptr;
@@ -98,8 +98,6 @@ int ensure_device()
     }
     return ABJ_OK;
 }
-
-namespace {
 
 // Checks that [p, p + bytes) lies inside one device (or managed) allocation.
 int check_dev_buf(const void* p, size_t bytes, const char* name)
@@ -138,10 +136,49 @@ int check_bounds(const int64_t* sb, int32_t n_seg, int64_t n_dict)
     return ABJ_OK;
 }
 
-constexpr int32_t kMaxM = 4096;
-constexpr int64_t kMaxN = (1LL << 31) - 1;
+int check_opts(const abj_opts* opts, abj_opts* out)
+{
+    abj_opts o = {ABJ_TIER_FP32, 0, 0, 0};
+    if (opts) o = *opts;
+    if (o.tier != ABJ_TIER_FP32 && o.tier != ABJ_TIER_BF16 && o.tier != ABJ_TIER_FP16)
+        return set_error(ABJ_EINVAL, "unknown tier %d", o.tier);
+    if (o.refine_k < 0 || o.refine_k > 8) return set_error(ABJ_EINVAL, "refine_k must be in 0..8");
+    if ((o.flags & ~ABJ_FLAG_NO_REFINE) != 0 || o.reserved != 0)
+        return set_error(ABJ_EINVAL, "unknown opts.flags bits or nonzero opts.reserved");
+    *out = o;
+    return ABJ_OK;
+}
 
-}  // namespace
+size_t query_scratch_bytes(int64_t n, int32_t m, int64_t WB, const abj_opts& o, const MfmaPlan& plan)
+{
+    (void)WB;
+    const int64_t W = n - m + 1;
+    size_t b = stats_scratch_bytes(n, W);
+    b += (sizeof(unsigned long long) * (size_t)W + 255) & ~size_t(255);
+    b += 256;  // slot descriptor
+    b += 256;  // tile counter
+    if (o.tier != ABJ_TIER_FP32) b += mfma_scratch_bytes(plan);
+    return b;
+}
+
+int join_query(const double* query, int64_t n, int32_t m, const SeriesDev& B, const abj_opts& o,
+               const MfmaPlan& plan, float* P, int64_t* I, Arena& ar, hipStream_t stream)
+{
+    SeriesDev A;
+    stats_carve(ar, n, m, &A);
+    unsigned long long* keys = ar.take<unsigned long long>((size_t)A.W);
+    Fp32Slot* dslot = ar.take<Fp32Slot>(1);
+    unsigned long long* counter = ar.take<unsigned long long>(1);
+    ABJ_TRY(stats_compute(query, &A, nullptr, 0, ar, stream));
+    if (o.tier != ABJ_TIER_FP32)
+        return join_mfma_run(A, B, plan, !(o.flags & ABJ_FLAG_NO_REFINE), P, I, ar, stream);
+    ABJ_TRY(fill_u64(keys, A.W, 0ull, stream));
+    Fp32Slot sl;
+    fp32_slot(A, B, keys, 0, &sl);
+    ABJ_HIP(hipMemcpyAsync(dslot, &sl, sizeof(sl), hipMemcpyHostToDevice, stream));
+    ABJ_TRY(join_fp32_batch(dslot, 1, fp32_slot_tiles(sl), m, sl.pairs, counter, stream));
+    return finalize_launch(A, B, keys, P, I, stream);
+}
 
 int stats_export(const SeriesDev& s, double* mu, double* sig, uint8_t* flags, hipStream_t stream);
 
@@ -221,13 +258,8 @@ extern "C" int ab_join(const double* query, int64_t n_query, const double* dict,
                        const abj_opts* opts, void* hip_stream)
 {
     // ---- validation: nothing is enqueued or written before this passes ----
-    abj_opts o = {ABJ_TIER_FP32, 0, 0, 0};
-    if (opts) o = *opts;
-    if (o.tier != ABJ_TIER_FP32 && o.tier != ABJ_TIER_BF16 && o.tier != ABJ_TIER_FP16)
-        return set_error(ABJ_EINVAL, "unknown tier %d", o.tier);
-    if (o.refine_k < 0 || o.refine_k > 8) return set_error(ABJ_EINVAL, "refine_k must be in 0..8");
-    if ((o.flags & ~ABJ_FLAG_NO_REFINE) != 0 || o.reserved != 0)
-        return set_error(ABJ_EINVAL, "unknown opts.flags bits or nonzero opts.reserved");
+    abj_opts o;
+    ABJ_TRY(check_opts(opts, &o));
     if (m < 2 || m > kMaxM) return set_error(ABJ_EINVAL, "m must be in [2, %d] (got %d)", kMaxM, m);
     if (n_query < m || n_query > kMaxN)
         return set_error(ABJ_EINVAL, "n_query must be in [m, 2^31-1] (got %lld)", (long long)n_query);
@@ -246,34 +278,18 @@ extern "C" int ab_join(const double* query, int64_t n_query, const double* dict,
 
     hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
     Arena ar(stream);
-    ar.reserve(stats_scratch_bytes(n_query, WA));
     ar.reserve(stats_scratch_bytes(n_dict, WB));
-    ar.reserve(sizeof(unsigned long long) * (size_t)WA);
     ar.reserve(sizeof(int64_t) * (size_t)(n_seg + 1));
-    ar.reserve(sizeof(Fp32Slot));
-    ar.reserve(sizeof(unsigned long long));
-    if (o.tier != ABJ_TIER_FP32) ar.reserve(mfma_scratch_bytes(plan));
+    ar.reserve(query_scratch_bytes(n_query, m, WB, o, plan));
     ABJ_TRY(ar.commit());
-    SeriesDev A, B;
-    stats_carve(ar, n_query, m, &A);
+    SeriesDev B;
     stats_carve(ar, n_dict, m, &B);
     for (int32_t sgi = 0; sgi < n_seg; ++sgi) {
         const int64_t len = seg_bounds[sgi + 1] - seg_bounds[sgi];
         if (len >= m) B.nvalid += len - m + 1;
     }
-    unsigned long long* keys = ar.take<unsigned long long>((size_t)WA);
     int64_t* dbounds = ar.take<int64_t>((size_t)(n_seg + 1));
     ABJ_HIP(hipMemcpyAsync(dbounds, seg_bounds, sizeof(int64_t) * (size_t)(n_seg + 1), hipMemcpyHostToDevice, stream));
-    ABJ_TRY(stats_compute(query, &A, nullptr, 0, ar, stream));
     ABJ_TRY(stats_compute(dict, &B, dbounds, n_seg, ar, stream));
-    if (o.tier != ABJ_TIER_FP32)
-        return join_mfma_run(A, B, plan, !(o.flags & ABJ_FLAG_NO_REFINE), P_AB, I_AB, ar, stream);
-    ABJ_TRY(fill_u64(keys, WA, 0ull, stream));
-    Fp32Slot sl;
-    fp32_slot(A, B, keys, 0, &sl);
-    Fp32Slot* dslot = ar.take<Fp32Slot>(1);
-    unsigned long long* counter = ar.take<unsigned long long>(1);
-    ABJ_HIP(hipMemcpyAsync(dslot, &sl, sizeof(sl), hipMemcpyHostToDevice, stream));
-    ABJ_TRY(join_fp32_batch(dslot, 1, fp32_slot_tiles(sl), m, sl.pairs, counter, stream));
-    return finalize_launch(A, B, keys, P_AB, I_AB, stream);
+    return join_query(query, n_query, m, B, o, plan, P_AB, I_AB, ar, stream);
 }

@@ -1,0 +1,647 @@
+// Resident dictionary and the serving scheduler.
+//
+// The inference phase of the paper (Alg. 2) joins every incoming series with
+// the same learned dictionary, so the dictionary and its per-window statistics
+// (one set per window length) stay in device memory.  The server turns a
+// stream of join requests of uneven lengths into GPU launches:
+//   * admission: a queued request is admitted (FIFO) when a slot is free and
+//     its device footprint fits in the memory budget;
+//   * continuous batching: every request admitted since the last launch goes
+//     into the next launch; FP32 requests share ONE persistent tile kernel
+//     (each request contributes its row-band x column-chunk tiles), so their
+//     work overlaps on the device; two launches are kept in flight on two
+//     streams, so requests arriving while one runs are launched at once;
+//   * completion: when a launch's event fires, its requests' results are
+//     copied to the host, their memory and slots are released and waiters
+//     are woken.
+// The host-simulation backend runs the same scheduler without any GPU call
+// (execution time = pairs / configured rate) so that admission, ordering,
+// cancellation and statistics can be tested on a machine without a GPU.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "abj_internal.hpp"
+
+using namespace abj;
+
+namespace abj {
+struct DictM {
+    int32_t m = 0;
+    SeriesDev B;
+    void* mem = nullptr;
+};
+}  // namespace abj
+
+struct abj_dict {
+    int device = 0;
+    int64_t n = 0;
+    std::vector<int64_t> bounds;
+    double* x = nullptr;
+    int64_t* dbounds = nullptr;
+    std::vector<DictM> per_m;
+    const DictM* find(int32_t m) const
+    {
+        for (auto& e : per_m)
+            if (e.m == m) return &e;
+        return nullptr;
+    }
+};
+
+static void dict_release(abj_dict* d)
+{
+    if (!d) return;
+    for (auto& e : d->per_m)
+        if (e.mem) (void)hipFree(e.mem);
+    if (d->x) (void)hipFree(d->x);
+    if (d->dbounds) (void)hipFree(d->dbounds);
+    delete d;
+}
+
+extern "C" int abj_dict_create(const double* dict, int64_t n_dict, const int64_t* seg_bounds, int32_t n_seg,
+                               const int32_t* ms, int32_t n_ms, abj_dict** out)
+{
+    if (!out) return set_error(ABJ_EINVAL, "out is NULL");
+    if (!dict) return set_error(ABJ_EINVAL, "dict is NULL");
+    if (n_dict < 1 || n_dict > kMaxN) return set_error(ABJ_EINVAL, "n_dict out of range");
+    ABJ_TRY(check_bounds(seg_bounds, n_seg, n_dict));
+    if (!ms || n_ms < 1 || n_ms > 16) return set_error(ABJ_EINVAL, "n_ms must be in 1..16");
+    for (int32_t a = 0; a < n_ms; ++a) {
+        if (ms[a] < 2 || ms[a] > kMaxM) return set_error(ABJ_EINVAL, "window length %d out of range", ms[a]);
+        for (int32_t b = 0; b < a; ++b)
+            if (ms[a] == ms[b]) return set_error(ABJ_EINVAL, "window length %d given twice", ms[a]);
+    }
+    ABJ_TRY(ensure_device());
+    hipPointerAttribute_t at;
+    bool on_device = false;
+    if (hipPointerGetAttributes(&at, dict) == hipSuccess)
+        on_device = at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged;
+    else
+        (void)hipGetLastError();
+
+    abj_dict* d = new abj_dict();
+    ABJ_HIP(hipGetDevice(&d->device));
+    d->n = n_dict;
+    d->bounds.assign(seg_bounds, seg_bounds + n_seg + 1);
+    int rc = ABJ_OK;
+    hipStream_t st = nullptr;
+    do {
+        if (hipMalloc(&d->x, sizeof(double) * (size_t)n_dict) != hipSuccess ||
+            hipMalloc(&d->dbounds, sizeof(int64_t) * (size_t)(n_seg + 1)) != hipSuccess) {
+            rc = set_error(ABJ_ENOMEM, "dictionary allocation failed");
+            break;
+        }
+        if (hipMemcpy(d->x, dict, sizeof(double) * (size_t)n_dict,
+                      on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(d->dbounds, seg_bounds, sizeof(int64_t) * (size_t)(n_seg + 1), hipMemcpyHostToDevice) !=
+                hipSuccess) {
+            rc = set_error(ABJ_EHIP, "dictionary copy failed");
+            break;
+        }
+        if (hipStreamCreate(&st) != hipSuccess) {
+            rc = set_error(ABJ_EHIP, "stream creation failed");
+            break;
+        }
+        for (int32_t a = 0; a < n_ms && rc == ABJ_OK; ++a) {
+            DictM e;
+            e.m = ms[a];
+            const int64_t W = n_dict >= e.m ? n_dict - e.m + 1 : 0;
+            const size_t bytes = stats_scratch_bytes(n_dict, W);
+            if (hipMalloc(&e.mem, bytes) != hipSuccess) {
+                rc = set_error(ABJ_ENOMEM, "dictionary statistics allocation failed");
+                break;
+            }
+            Arena ar(e.mem, bytes);
+            stats_carve(ar, n_dict, e.m, &e.B);
+            for (int32_t sgi = 0; sgi < n_seg; ++sgi) {
+                const int64_t len = seg_bounds[sgi + 1] - seg_bounds[sgi];
+                if (len >= e.m) e.B.nvalid += len - e.m + 1;
+            }
+            rc = stats_compute(d->x, &e.B, d->dbounds, n_seg, ar, st);
+            d->per_m.push_back(e);
+        }
+        if (rc == ABJ_OK && hipStreamSynchronize(st) != hipSuccess) rc = set_error(ABJ_EHIP, "statistics failed");
+    } while (0);
+    if (st) (void)hipStreamDestroy(st);
+    if (rc != ABJ_OK) {
+        dict_release(d);
+        return rc;
+    }
+    *out = d;
+    return ABJ_OK;
+}
+
+extern "C" int abj_dict_free(abj_dict* d)
+{
+    if (!d) return set_error(ABJ_EINVAL, "dictionary is NULL");
+    dict_release(d);
+    return ABJ_OK;
+}
+
+extern "C" int ab_join_dict(const abj_dict* d, const double* query, int64_t n_query, int32_t m, float* P_AB,
+                            int64_t* I_AB, const abj_opts* opts, void* hip_stream)
+{
+    if (!d) return set_error(ABJ_EINVAL, "dictionary is NULL");
+    abj_opts o;
+    ABJ_TRY(check_opts(opts, &o));
+    const DictM* e = d->find(m);
+    if (!e) return set_error(ABJ_EINVAL, "m = %d is not a window length of this dictionary", m);
+    if (n_query < m || n_query > kMaxN)
+        return set_error(ABJ_EINVAL, "n_query must be in [m, 2^31-1] (got %lld)", (long long)n_query);
+    const int64_t WA = n_query - m + 1;
+    ABJ_TRY(check_dev_buf(query, sizeof(double) * (size_t)n_query, "query"));
+    ABJ_TRY(check_dev_buf(P_AB, sizeof(float) * (size_t)WA, "P_AB"));
+    ABJ_TRY(check_dev_buf(I_AB, sizeof(int64_t) * (size_t)WA, "I_AB"));
+    MfmaPlan plan;
+    if (o.tier != ABJ_TIER_FP32) ABJ_TRY(mfma_plan(WA, e->B.W, m, o.tier, o.refine_k, &plan));
+    ABJ_TRY(ensure_device());
+    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+    Arena ar(stream);
+    ar.reserve(query_scratch_bytes(n_query, m, e->B.W, o, plan));
+    ABJ_TRY(ar.commit());
+    return join_query(query, n_query, m, e->B, o, plan, P_AB, I_AB, ar, stream);
+}
+
+// ---------------------------------------------------------------------------
+// Server
+// ---------------------------------------------------------------------------
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+enum ReqState { kQueued = 0, kRunning = 1, kDone = 2, kCanceled = 3 };
+
+struct Req {
+    uint64_t id = 0;
+    std::vector<double> q;
+    int64_t n = 0, W = 0;
+    int32_t m = 0;
+    const DictM* dm = nullptr;
+    int state = kQueued;
+    size_t mem = 0;
+    MfmaPlan plan;
+    abj_req_stats st{};
+    std::vector<float> P;
+    std::vector<int64_t> I;
+    // device side, valid while running
+    char* dmem = nullptr;
+    SeriesDev A;
+    unsigned long long* keys = nullptr;
+    float* dP = nullptr;
+    int64_t* dI = nullptr;
+};
+
+struct Batch {
+    std::vector<Req*> reqs;
+    int stream = 0;
+    hipEvent_t ev = nullptr;
+    void* aux = nullptr;  // slot descriptors + tile counter
+    double t_sim_done = 0;
+    int status = ABJ_OK;
+};
+
+}  // namespace
+
+struct abj_server {
+    const abj_dict* d = nullptr;
+    abj_server_opts o{};
+    abj_opts jo{};
+    int device = 0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::map<uint64_t, std::unique_ptr<Req>> reqs;
+    std::deque<uint64_t> queue;
+    uint64_t next_id = 1;
+    int active = 0;
+    int64_t mem_used = 0;
+    bool stop = false;
+    std::thread th;
+    hipStream_t streams[2] = {nullptr, nullptr};
+    Clock::time_point t0;
+    abj_server_stats stats{};
+    double t_first_launch = -1, t_last_done = 0;
+    std::vector<double> lat;
+
+    double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+    bool sim() const { return o.backend == 1; }
+};
+
+namespace {
+
+size_t req_bytes(const abj_server* s, int64_t n, int32_t m, MfmaPlan* plan)
+{
+    const int64_t W = n - m + 1;
+    size_t b = 0;
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    b += al((size_t)n * sizeof(double));  // query copy
+    b += al((size_t)W * sizeof(float)) + al((size_t)W * sizeof(int64_t));  // outputs
+    int64_t WB = 0;
+    if (s->sim()) {
+        WB = s->o.sim_dict_windows;
+    } else {
+        const DictM* e = s->d->find(m);
+        WB = e ? e->B.W : 0;
+    }
+    if (s->jo.tier != ABJ_TIER_FP32 && !s->sim()) mfma_plan(W, WB, m, s->jo.tier, 0, plan);
+    b += query_scratch_bytes(n, m, WB, s->jo, *plan);
+    return b;
+}
+
+// Launch one batch on the GPU: per request, copy the query and compute its
+// statistics; then one persistent tile kernel over all FP32 requests (or one
+// launch per request in the 16-bit tiers); then each request's row epilogue.
+int launch_batch(abj_server* s, Batch& b)
+{
+    hipStream_t st = s->streams[b.stream];
+    std::vector<Fp32Slot> slots;
+    int64_t tiles = 0, pairs = 0;
+    int max_m = 2;
+    for (Req* r : b.reqs) {
+        ABJ_HIP(hipMallocAsync(reinterpret_cast<void**>(&r->dmem), r->mem, st));
+        Arena ar(r->dmem, r->mem);
+        double* dq = ar.take<double>((size_t)r->n);
+        r->dP = ar.take<float>((size_t)r->W);
+        r->dI = ar.take<int64_t>((size_t)r->W);
+        ABJ_HIP(hipMemcpyAsync(dq, r->q.data(), sizeof(double) * (size_t)r->n, hipMemcpyHostToDevice, st));
+        if (s->jo.tier != ABJ_TIER_FP32) {
+            ABJ_TRY(join_query(dq, r->n, r->m, r->dm->B, s->jo, r->plan, r->dP, r->dI, ar, st));
+            continue;
+        }
+        stats_carve(ar, r->n, r->m, &r->A);
+        r->keys = ar.take<unsigned long long>((size_t)r->W);
+        ar.take<Fp32Slot>(1);
+        ar.take<unsigned long long>(1);
+        ABJ_TRY(stats_compute(dq, &r->A, nullptr, 0, ar, st));
+        ABJ_TRY(fill_u64(r->keys, r->W, 0ull, st));
+        Fp32Slot sl;
+        fp32_slot(r->A, r->dm->B, r->keys, tiles, &sl);
+        tiles += fp32_slot_tiles(sl);
+        pairs += sl.pairs;
+        max_m = std::max(max_m, (int)r->m);
+        slots.push_back(sl);
+    }
+    if (!slots.empty()) {
+        const size_t sb = sizeof(Fp32Slot) * slots.size();
+        const size_t aux = ((sb + 255) & ~size_t(255)) + 256;
+        ABJ_HIP(hipMallocAsync(&b.aux, aux, st));
+        Fp32Slot* dslots = static_cast<Fp32Slot*>(b.aux);
+        unsigned long long* counter =
+            reinterpret_cast<unsigned long long*>(static_cast<char*>(b.aux) + ((sb + 255) & ~size_t(255)));
+        ABJ_HIP(hipMemcpyAsync(dslots, slots.data(), sb, hipMemcpyHostToDevice, st));
+        ABJ_TRY(join_fp32_batch(dslots, (int)slots.size(), tiles, max_m, pairs, counter, st));
+        for (Req* r : b.reqs) ABJ_TRY(finalize_launch(r->A, r->dm->B, r->keys, r->dP, r->dI, st));
+    }
+    ABJ_HIP(hipEventCreateWithFlags(&b.ev, hipEventDisableTiming));
+    ABJ_HIP(hipEventRecord(b.ev, st));
+    return ABJ_OK;
+}
+
+// Copy a finished batch's results to the host and release its memory.
+int collect_batch(abj_server* s, Batch& b)
+{
+    hipStream_t st = s->streams[b.stream];
+    int rc = b.status;
+    for (Req* r : b.reqs) {
+        r->P.resize((size_t)r->W);
+        r->I.resize((size_t)r->W);
+        if (rc == ABJ_OK && r->dP) {
+            if (hipMemcpyAsync(r->P.data(), r->dP, sizeof(float) * (size_t)r->W, hipMemcpyDeviceToHost, st) !=
+                    hipSuccess ||
+                hipMemcpyAsync(r->I.data(), r->dI, sizeof(int64_t) * (size_t)r->W, hipMemcpyDeviceToHost, st) !=
+                    hipSuccess)
+                rc = set_error(ABJ_EHIP, "result copy failed");
+        }
+    }
+    if (hipStreamSynchronize(st) != hipSuccess && rc == ABJ_OK) rc = set_error(ABJ_EHIP, "batch failed");
+    for (Req* r : b.reqs) {
+        if (r->dmem) (void)hipFreeAsync(r->dmem, st);
+        r->dmem = nullptr;
+    }
+    if (b.aux) (void)hipFreeAsync(b.aux, st);
+    if (b.ev) (void)hipEventDestroy(b.ev);
+    return rc;
+}
+
+void sim_fill(abj_server* s, Req* r)
+{
+    r->P.resize((size_t)r->W);
+    r->I.resize((size_t)r->W);
+    const int64_t wb = s->o.sim_dict_windows > 0 ? s->o.sim_dict_windows : 1;
+    for (int64_t i = 0; i < r->W; ++i) {
+        r->P[(size_t)i] = (float)((i * 7 + (int64_t)r->id) % 100) * 0.1f;
+        r->I[(size_t)i] = i % wb;
+    }
+}
+
+void scheduler(abj_server* s)
+{
+    if (!s->sim()) (void)hipSetDevice(s->device);
+    std::deque<Batch> inflight;
+    int next_stream = 0;
+    int64_t batch_no = 0;
+    for (;;) {
+        Batch b;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            auto admissible = [&] {
+                if (s->queue.empty() || s->active >= s->o.max_slots) return false;
+                const Req* r = s->reqs[s->queue.front()].get();
+                return s->mem_used + (int64_t)r->mem <= s->o.mem_budget;
+            };
+            if (inflight.empty()) {
+                s->cv_work.wait(lk, [&] { return s->stop || admissible(); });
+                if (s->stop && !admissible()) break;
+            } else if (inflight.size() < 2 && !admissible()) {
+                // keep polling the running launches, but wake at once for arrivals
+                s->cv_work.wait_for(lk, std::chrono::microseconds(50), [&] { return s->stop || admissible(); });
+            }
+            if (inflight.size() < 2) {
+                while (admissible()) {
+                    Req* r = s->reqs[s->queue.front()].get();
+                    s->queue.pop_front();
+                    s->active += 1;
+                    s->mem_used += (int64_t)r->mem;
+                    r->state = kRunning;
+                    r->st.t_admit = s->now();
+                    b.reqs.push_back(r);
+                }
+            }
+        }
+        if (!b.reqs.empty()) {
+            b.stream = next_stream;
+            next_stream ^= 1;
+            const double t = s->now();
+            int64_t pairs = 0;
+            for (Req* r : b.reqs) {
+                r->st.t_start = t;
+                r->st.batch = (int32_t)batch_no;
+                pairs += r->st.pairs;
+            }
+            ++batch_no;
+            if (s->t_first_launch < 0) s->t_first_launch = t;
+            if (s->sim()) {
+                const double start = inflight.empty() ? t : std::max(t, inflight.back().t_sim_done);
+                b.t_sim_done = start + (double)pairs / (s->o.sim_pairs_per_s > 0 ? s->o.sim_pairs_per_s : 1e12);
+            } else {
+                b.status = launch_batch(s, b);
+            }
+            inflight.push_back(std::move(b));
+        }
+        // completion: oldest launch first
+        while (!inflight.empty()) {
+            Batch& ob = inflight.front();
+            bool done;
+            if (s->sim()) {
+                done = s->now() >= ob.t_sim_done;
+                if (!done && inflight.size() >= 2) {
+                    std::this_thread::sleep_for(std::chrono::duration<double>(ob.t_sim_done - s->now()));
+                    done = true;
+                }
+            } else if (ob.status != ABJ_OK || !ob.ev) {
+                done = true;
+            } else {
+                hipError_t q = hipEventQuery(ob.ev);
+                if (q == hipErrorNotReady) (void)hipGetLastError();  // not an error: do not leave it pending
+                done = q != hipErrorNotReady;
+                if (!done && inflight.size() >= 2) {
+                    (void)hipEventSynchronize(ob.ev);
+                    done = true;
+                }
+            }
+            if (!done) break;
+            int rc = ob.status;
+            if (s->sim()) {
+                for (Req* r : ob.reqs) sim_fill(s, r);
+            } else {
+                rc = collect_batch(s, ob);
+            }
+            {
+                std::lock_guard<std::mutex> lk(s->mu);
+                const double t = s->now();
+                for (Req* r : ob.reqs) {
+                    r->state = kDone;
+                    r->st.status = rc;
+                    r->st.t_done = t;
+                    r->q.clear();
+                    r->q.shrink_to_fit();
+                    s->active -= 1;
+                    s->mem_used -= (int64_t)r->mem;
+                    if (rc == ABJ_OK) {
+                        s->stats.completed += 1;
+                        s->stats.pairs += r->st.pairs;
+                        s->lat.push_back(r->st.t_done - r->st.t_arrive);
+                    }
+                }
+                s->stats.batches += 1;
+                s->t_last_done = t;
+            }
+            s->cv_done.notify_all();
+            s->cv_work.notify_all();
+            inflight.pop_front();
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" int abj_server_create(const abj_dict* d, const abj_server_opts* opts, abj_server** out)
+{
+    if (!opts || !out) return set_error(ABJ_EINVAL, "opts and out must not be NULL");
+    const abj_server_opts& o = *opts;
+    if (o.max_slots < 1) return set_error(ABJ_EINVAL, "max_slots must be >= 1");
+    if (o.mem_budget <= 0) return set_error(ABJ_EINVAL, "mem_budget must be > 0");
+    if (o.backend != 0 && o.backend != 1) return set_error(ABJ_EINVAL, "unknown backend %d", o.backend);
+    abj_opts jo = {o.tier, 0, 0, 0};
+    ABJ_TRY(check_opts(&jo, &jo));
+    if (o.backend == 0 && !d) return set_error(ABJ_EINVAL, "the GPU backend needs a dictionary");
+    if (o.backend == 1) {
+        if (d) return set_error(ABJ_EINVAL, "the simulation backend takes no dictionary");
+        if (o.sim_n_ms < 1 || o.sim_n_ms > 8) return set_error(ABJ_EINVAL, "sim_n_ms must be in 1..8");
+    }
+    abj_server* s = new abj_server();
+    s->d = d;
+    s->o = o;
+    s->jo = jo;
+    s->t0 = Clock::now();
+    if (o.backend == 0) {
+        int rc = ensure_device();
+        if (rc == ABJ_OK && hipGetDevice(&s->device) != hipSuccess) rc = set_error(ABJ_EHIP, "hipGetDevice failed");
+        for (int k = 0; k < 2 && rc == ABJ_OK; ++k)
+            if (hipStreamCreate(&s->streams[k]) != hipSuccess) rc = set_error(ABJ_EHIP, "stream creation failed");
+        if (rc != ABJ_OK) {
+            for (auto& st : s->streams)
+                if (st) (void)hipStreamDestroy(st);
+            delete s;
+            return rc;
+        }
+    }
+    s->th = std::thread(scheduler, s);
+    *out = s;
+    return ABJ_OK;
+}
+
+extern "C" int abj_submit(abj_server* s, const double* query_host, int64_t n_query, int32_t m, uint64_t* req_id)
+{
+    if (!s || !query_host || !req_id) return set_error(ABJ_EINVAL, "NULL argument");
+    int64_t WB = 0;
+    bool m_ok = false;
+    if (s->sim()) {
+        for (int a = 0; a < s->o.sim_n_ms; ++a) m_ok |= s->o.sim_ms[a] == m;
+        WB = s->o.sim_dict_windows;
+    } else if (const DictM* e = s->d->find(m)) {
+        m_ok = true;
+        WB = e->B.W;
+    }
+    auto reject = [&](int code, const char* msg) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stats.rejected += 1;
+        return set_error(code, "%s", msg);
+    };
+    if (!m_ok) return reject(ABJ_EINVAL, "m is not a window length of the dictionary");
+    if (n_query < m || n_query > kMaxN) return reject(ABJ_EINVAL, "n_query must be >= m");
+    auto r = std::make_unique<Req>();
+    r->n = n_query;
+    r->m = m;
+    r->W = n_query - m + 1;
+    r->dm = s->sim() ? nullptr : s->d->find(m);
+    r->mem = req_bytes(s, n_query, m, &r->plan);
+    if ((int64_t)r->mem > s->o.mem_budget) return reject(ABJ_ENOMEM, "request exceeds the memory budget");
+    const int64_t nvalid = s->sim() ? WB : r->dm->B.nvalid;
+    r->st.pairs = r->W * nvalid;
+    r->q.assign(query_host, query_host + n_query);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->stop) return set_error(ABJ_EINVAL, "server is shutting down");
+        r->id = s->next_id++;
+        r->st.t_arrive = s->now();
+        r->st.batch = -1;
+        *req_id = r->id;
+        s->queue.push_back(r->id);
+        s->stats.submitted += 1;
+        s->reqs[r->id] = std::move(r);
+    }
+    s->cv_work.notify_all();
+    return ABJ_OK;
+}
+
+extern "C" int abj_wait(abj_server* s, uint64_t id, int32_t timeout_ms)
+{
+    if (!s) return set_error(ABJ_EINVAL, "server is NULL");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(id);
+    if (it == s->reqs.end()) return set_error(ABJ_ENOTFOUND, "unknown request %llu", (unsigned long long)id);
+    Req* r = it->second.get();
+    auto fin = [&] { return r->state == kDone || r->state == kCanceled; };
+    if (timeout_ms < 0) {
+        s->cv_done.wait(lk, fin);
+    } else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), fin)) {
+        return set_error(ABJ_ETIMEOUT, "request %llu not finished", (unsigned long long)id);
+    }
+    if (r->state == kCanceled) return set_error(ABJ_ECANCELED, "request %llu was canceled", (unsigned long long)id);
+    return r->st.status;
+}
+
+extern "C" int abj_result(abj_server* s, uint64_t id, float* P_host, int64_t* I_host, abj_req_stats* st)
+{
+    if (!s) return set_error(ABJ_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(id);
+    if (it == s->reqs.end()) return set_error(ABJ_ENOTFOUND, "unknown request %llu", (unsigned long long)id);
+    Req* r = it->second.get();
+    if (r->state != kDone && r->state != kCanceled)
+        return set_error(ABJ_EBUSY, "request %llu is not finished", (unsigned long long)id);
+    if (st) *st = r->st;
+    if (r->state == kDone && r->st.status == ABJ_OK) {
+        if (P_host) memcpy(P_host, r->P.data(), sizeof(float) * (size_t)r->W);
+        if (I_host) memcpy(I_host, r->I.data(), sizeof(int64_t) * (size_t)r->W);
+    }
+    const int rc = r->state == kCanceled ? ABJ_ECANCELED : r->st.status;
+    s->reqs.erase(it);
+    if (rc != ABJ_OK) return set_error(rc, "request %llu did not complete", (unsigned long long)id);
+    return ABJ_OK;
+}
+
+extern "C" int abj_cancel(abj_server* s, uint64_t id)
+{
+    if (!s) return set_error(ABJ_EINVAL, "server is NULL");
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->reqs.find(id);
+        if (it == s->reqs.end()) return set_error(ABJ_ENOTFOUND, "unknown request %llu", (unsigned long long)id);
+        Req* r = it->second.get();
+        if (r->state != kQueued) return set_error(ABJ_EBUSY, "request %llu is already running", (unsigned long long)id);
+        s->queue.erase(std::find(s->queue.begin(), s->queue.end(), id));
+        r->state = kCanceled;
+        r->st.status = ABJ_ECANCELED;
+        r->st.t_done = s->now();
+        s->stats.canceled += 1;
+    }
+    s->cv_done.notify_all();
+    s->cv_work.notify_all();
+    return ABJ_OK;
+}
+
+extern "C" int abj_server_drain(abj_server* s, int32_t timeout_ms)
+{
+    if (!s) return set_error(ABJ_EINVAL, "server is NULL");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto idle = [&] { return s->queue.empty() && s->active == 0; };
+    if (timeout_ms < 0) {
+        s->cv_done.wait(lk, idle);
+    } else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), idle)) {
+        return set_error(ABJ_ETIMEOUT, "server still busy");
+    }
+    return ABJ_OK;
+}
+
+extern "C" int abj_server_stats_get(abj_server* s, abj_server_stats* out)
+{
+    if (!s || !out) return set_error(ABJ_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    abj_server_stats st = s->stats;
+    st.busy_s = s->t_first_launch >= 0 ? s->t_last_done - s->t_first_launch : 0.0;
+    std::vector<double> v = s->lat;
+    std::sort(v.begin(), v.end());
+    auto pct = [&](double p) {
+        if (v.empty()) return 0.0;
+        size_t k = (size_t)ceil(p * (double)v.size()) - 1;
+        return v[std::min(k, v.size() - 1)];
+    };
+    st.p50_s = pct(0.50);
+    st.p99_s = pct(0.99);
+    st.max_s = v.empty() ? 0.0 : v.back();
+    *out = st;
+    return ABJ_OK;
+}
+
+extern "C" int abj_server_destroy(abj_server* s)
+{
+    if (!s) return set_error(ABJ_EINVAL, "server is NULL");
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        for (uint64_t id : s->queue) {
+            Req* r = s->reqs[id].get();
+            r->state = kCanceled;
+            r->st.status = ABJ_ECANCELED;
+            s->stats.canceled += 1;
+        }
+        s->queue.clear();
+    }
+    s->cv_work.notify_all();
+    s->cv_done.notify_all();
+    if (s->th.joinable()) s->th.join();
+    for (auto& st : s->streams)
+        if (st) (void)hipStreamDestroy(st);
+    delete s;
+    return ABJ_OK;
+}

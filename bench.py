@@ -52,31 +52,108 @@ def valid_windows(bounds, m):
     return int(sum(max(0, int(b[s + 1] - b[s]) - m + 1) for s in range(len(b) - 1)))
 
 
-def cpu_baseline(w, P_gpu, I_gpu, target_s: float, threads: int):
-    """Time the FP64 oracle on a bounded row sample; also report the GPU error there."""
+def cpu_baseline(w, results, target_s: float, threads: int):
+    """Time the FP64 oracle on a bounded row sample; report each GPU tier's error there.
+
+    ``results``: {tier: (P, I)} host arrays of the full GPU result.  The oracle
+    is timed on a 64-row call first, then on as many rows as fit in about
+    ``target_s`` seconds."""
     import oracle
 
     q, d, b, m = w["query"], w["dict"], w["bounds"], w["m"]
     W = len(q) - m + 1
     V = valid_windows(b, m)
     rng = np.random.default_rng(12345)
-    cal = np.sort(rng.choice(W, 64, replace=False))
     t0 = time.perf_counter()
-    oracle.ab_join(q, d, b, m, rows=cal, threads=threads)
-    t_cal = time.perf_counter() - t0
-    nrows = int(np.clip(64 * target_s / max(t_cal, 1e-3), 64, W))
+    oracle.ab_join(q, d, b, m, rows=np.sort(rng.choice(W, 64, replace=False)), threads=threads)
+    t64 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.ab_join(q, d, b, m, rows=np.sort(rng.choice(W, 256, replace=False)), threads=threads)
+    t256 = time.perf_counter() - t0
+    per_row = max((t256 - t64) / 192.0, 1e-6)  # the call's fixed cost cancels
+    nrows = int(np.clip(target_s / per_row, 256, W))
     rows = np.sort(rng.choice(W, nrows, replace=False))
     t0 = time.perf_counter()
-    Po, Io = oracle.ab_join(q, d, b, m, rows=rows, threads=threads)
+    Po, Io, P2o = oracle.ab_join(q, d, b, m, rows=rows, threads=threads, second=True)
     dt = time.perf_counter() - t0
-    err = np.abs(P_gpu[rows].astype(np.float64) - Po)
+    errs = {}
+    for tier, (P, I) in results.items():
+        err = np.abs(P[rows].astype(np.float64) - Po)
+        clear = (P2o - Po) > 1e-3
+        errs[tier] = {"rows": nrows, "max_abs": float(err.max()), "mean_abs": float(err.mean()),
+                      "index_match_clear_rows": float(np.mean(I[rows][clear] == Io[clear]))}
     return (
         {"value": nrows * V / dt, "unit": "pair-distances/s", "cores": threads, "kind": "oracle",
          "sample": f"{nrows} random query rows x {V} dictionary windows of the same workload, "
                    f"{dt:.1f} s wall, FP64 brute force, OpenMP {threads} threads"},
-        {"rows": nrows, "max_abs": float(err.max()), "mean_abs": float(err.mean()),
-         "index_match": float(np.mean(I_gpu[rows] == Io))},
+        errs,
     )
+
+
+def time_tier(abjoin, q, d, bounds, m, tier, steps, warmup, P, I):
+    import torch
+
+    for _ in range(warmup):
+        abjoin.ab_join(q, d, bounds, m, tier=tier, out=(P, I))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        abjoin.ab_join(q, d, bounds, m, tier=tier, out=(P, I))
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def serving(abjoin, synth, tiers, n_req: int, fracs=(0.5, 0.8, 0.95)):
+    """Serving workload: a resident dictionary of 64 x 1,000 ECG-like samples;
+    requests with log-uniform lengths in [1,024, 65,536] and m drawn from
+    {64, 128, 256}.  Saturation throughput first (all requests at once), then
+    Poisson arrivals at fractions of the saturation rate; p50/p99 latency from
+    submit to results on the host."""
+    import threading
+
+    w = synth.WORKLOADS["serve_dict64x1000"]()
+    dct = abjoin.Dictionary(w["dict"], w["bounds"], (64, 128, 256))
+    pool = synth.ecg_like(1 << 22, synth.rng_for(3, 0))
+    out = {"workload": "serve_dict64x1000", "requests": n_req, "dict_segments": 64, "segment_samples": 1000,
+           "query_samples": "log-uniform 1024..65536", "m": [64, 128, 256], "tiers": {}}
+    for tier in tiers:
+        def run(qps):
+            sched = synth.serving_schedule(n_req, qps if qps else 1e9, synth.rng_for(4, int(qps or 0)))
+            offs = synth.rng_for(4, 99).integers(0, len(pool) - 65536, n_req)
+            srv = abjoin.Server(dct, tier=tier, max_slots=512, mem_budget=2 << 30)
+            ids = [None] * n_req
+            t0 = time.perf_counter()
+
+            def feeder():
+                for k, r in enumerate(sched):
+                    if qps:
+                        dt = r.arrival_s - (time.perf_counter() - t0)
+                        if dt > 0:
+                            time.sleep(dt)
+                    ids[k] = srv.submit(pool[offs[k]:offs[k] + r.length], r.m)
+
+            th = threading.Thread(target=feeder)
+            th.start()
+            th.join()
+            assert srv.drain(600000) == abjoin.ABJ_OK
+            st = srv.stats()
+            for i in ids:
+                srv.result(i)
+            srv.close()
+            return st
+
+        sat = run(None)
+        sat_qps = sat["completed"] / sat["busy_s"]
+        rec = {"saturation_pairs_per_s": sat["pairs"] / sat["busy_s"], "saturation_qps": sat_qps,
+               "batches": sat["batches"], "levels": []}
+        for f in fracs:
+            st = run(f * sat_qps)
+            rec["levels"].append({"qps": f * sat_qps, "load": f, "p50_ms": st["p50_s"] * 1e3,
+                                  "p99_ms": st["p99_s"] * 1e3, "max_ms": st["max_s"] * 1e3,
+                                  "pairs_per_s": st["pairs"] / st["busy_s"], "batches": st["batches"]})
+        out["tiers"][tier] = rec
+    dct.close()
+    return out
 
 
 def main():
@@ -87,6 +164,9 @@ def main():
     ap.add_argument("--tier", default="fp32", choices=["fp32"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tiers", action="store_true", help="skip the BF16/FP16 comparison")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving workload")
+    ap.add_argument("--serve-requests", type=int, default=4096)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="after the timed steps, run one device-to-device copy of this many bytes "
                          "(reference dispatch for scaling HBM counters)")
@@ -160,12 +240,23 @@ def main():
                          os.path.join(ROOT, "paper_2112_12965_amd", "csrc", "join_fp32.hip"),
                          os.path.join(ROOT, "profiles", "k_join_fp32_ecg131k_dict16x2000_m256_hbm_counters.md"))},
     }
+    results = {"fp32": (P.cpu().numpy(), I.cpu().numpy())}
+    if not args.no_tiers:
+        out["tiers"] = {"fp32": {"pairs_per_s": out["value"], "ms_per_step": out["ms_per_step"]}}
+        for tier in ("bf16", "fp16"):
+            Pt = torch.empty_like(P)
+            It = torch.empty_like(I)
+            dtt = time_tier(abjoin, q, d, bounds, m, tier, max(args.steps // 5, 3), 2, Pt, It)
+            out["tiers"][tier] = {"pairs_per_s": pairs / dtt, "ms_per_step": dtt * 1e3,
+                                  "vs_fp32": (pairs / dtt) / out["value"]}
+            results[tier] = (Pt.cpu().numpy(), It.cpu().numpy())
     if not args.no_cpu:
-        Ph, Ih = P.cpu().numpy(), I.cpu().numpy()
         threads = min(16, os.cpu_count() or 1)
-        cb, err = cpu_baseline(w, Ph, Ih, args.cpu_seconds, threads)
+        cb, errs = cpu_baseline(w, results, args.cpu_seconds, threads)
         out["cpu_baseline"] = cb
-        out["error_vs_oracle"] = err
+        out["error_vs_oracle"] = errs
+    if not args.no_serving:
+        out["serving"] = serving(abjoin, synth, ("fp32", "bf16"), args.serve_requests)
     print(json.dumps(out), flush=True)
 
 

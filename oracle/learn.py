@@ -1,0 +1,118 @@
+"""Oracle of the learning phase (Alg. 1, LearnDictionary) -- TEST INFRASTRUCTURE ONLY.
+
+Plain Python over the FP64 primitives of this package, in the order of the
+paper's listing:
+
+  P_B  <- self-join of T_B                                   (Alg. 1 line 3)
+  S    <- 0, D <- {}                                         (lines 4-5)
+  loop:
+    P'  <- P_B - S                                           (line 7)
+    P'[i] <- inf for |i - s| <= floor(m/2), s = start of every
+             window already chosen                           (lines 8-10)
+    j   <- argmin P'                                         (line 11)
+    add T_B[j:j+m] with context to D                         (line 12)
+    stop if the terminal condition holds                     (lines 13-14)
+    S'  <- distance profile of T_B against T_B[j:j+m]        (line 15)
+    S   <- S' if this is the first element, else min(S, S')  (lines 16-19)
+
+Readings where the paper leaves a choice (listed in the design notes):
+  * context: the element is ceil(k m) samples (k = 1.5 in the paper), centred on
+    the chosen window and clipped to the series;
+  * exclusion: |i - s| <= floor(m/2) around each chosen window start s, the
+    same zone the self-join uses for trivial matches;
+  * overlapping (or touching) elements are merged into one segment;
+  * memory condition: stop once the merged dictionary holds at least
+    (1 - space_saving) n samples; e_max condition: stop once e_max of the
+    current dictionary (Def. 10, computed exactly with the AB-join) is <= the
+    target; either way the element of the stopping iteration is kept;
+  * windows never chosen: those already excluded, and none when every P' is
+    infinite (the loop then ends).
+
+``forced`` replays a given sequence of choices (lockstep checks against the
+GPU): at each step the forced index must be an argmin of P' within ``tie_tol``
+and is used in place of the oracle's own argmin.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import ab_join, dist_profile, self_join
+
+
+def merge_elements(elements):
+    """Merge [start, end) intervals that overlap or touch; sorted by start."""
+    out = []
+    for a, b in sorted(elements):
+        if out and a <= out[-1][1]:
+            out[-1][1] = max(out[-1][1], b)
+        else:
+            out.append([a, b])
+    return [tuple(e) for e in out]
+
+
+def element_of(j, n, m, k):
+    L = min(n, max(m, int(math.ceil(k * m))))
+    c0 = j - (L - m) // 2
+    c0 = min(max(c0, 0), n - L)
+    return c0, c0 + L
+
+
+def dictionary_of(T, segs):
+    d = np.concatenate([T[a:b] for a, b in segs]) if segs else np.zeros(0)
+    bounds = np.concatenate([[0], np.cumsum([b - a for a, b in segs])]).astype(np.int64)
+    return d, bounds, np.array([a for a, _ in segs], dtype=np.int64)
+
+
+def e_max_of(T, segs, m):
+    """Def. 10: max over the windows of T of the distance to the dictionary's windows."""
+    d, bounds, _ = dictionary_of(T, segs)
+    if len(d) < m:
+        return math.inf
+    P, _ = ab_join(T, d, bounds, m)
+    return float(np.max(P))
+
+
+def learn_dictionary(T, m, k=1.5, stop="space_saving", value=0.9, max_iters=None, forced=None, tie_tol=1e-6):
+    """Returns dict(segments, chosen, dictionary, bounds, orig_start, e_max, p_b)."""
+    T = np.asarray(T, dtype=np.float64)
+    n = len(T)
+    W = n - m + 1
+    excl = m // 2
+    P_B, _ = self_join(T, m, excl)
+    S = np.zeros(W)
+    first = True
+    blocked = np.zeros(W, dtype=bool)
+    chosen, elements = [], []
+    max_iters = W if max_iters is None else max_iters
+    for it in range(max_iters):
+        if forced is not None and it >= len(forced):
+            raise AssertionError(f"the replayed run stopped after {len(forced)} steps; the oracle continues")
+        Pp = P_B - S
+        Pp[blocked] = np.inf
+        Pp[~np.isfinite(P_B)] = np.inf
+        if not np.isfinite(Pp).any():
+            break
+        j = int(np.argmin(Pp))
+        if forced is not None:
+            jf = int(forced[it])
+            if not (Pp[jf] <= Pp[j] + tie_tol):
+                raise AssertionError(f"step {it}: forced {jf} (P'={Pp[jf]}) is not an argmin (P'[{j}]={Pp[j]})")
+            j = jf
+        chosen.append(j)
+        blocked[max(0, j - excl):min(W, j + excl + 1)] = True
+        elements.append(element_of(j, n, m, k))
+        segs = merge_elements(elements)
+        size = sum(b - a for a, b in segs)
+        if stop == "space_saving" and size >= (1.0 - value) * n:
+            break
+        if stop == "e_max" and e_max_of(T, segs, m) <= value:
+            break
+        Sp = dist_profile(T, m, T[j:j + m])
+        S = Sp if first else np.minimum(S, Sp)
+        first = False
+    segs = merge_elements(elements)
+    d, bounds, orig = dictionary_of(T, segs)
+    return dict(segments=segs, chosen=chosen, dictionary=d, bounds=bounds, orig_start=orig,
+                e_max=e_max_of(T, segs, m), p_b=P_B)

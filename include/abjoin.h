@@ -122,6 +122,73 @@ int abj_window_stats(const double* x, int64_t n, int32_t m, double* mu, double* 
 int ab_join(const double* query, int64_t n_query, const double* dict, int64_t n_dict, const int64_t* seg_bounds,
             int32_t n_seg, int32_t m, float* P_AB, int64_t* I_AB, const abj_opts* opts, void* hip_stream);
 
+/*
+ * Self-join matrix profile of one series (the P_B of the learning phase,
+ * Alg. 1, and Def. 7 with A = B): for every window i of x, the nearest window
+ * j with |i - j| > excl (trivial matches excluded).  excl = m/2 (rounded down)
+ * is the zone the learning phase uses; excl < 0 selects it.
+ *   x   device, n doubles
+ *   P   device, n-m+1 floats (out)        I  device, n-m+1 int64 (out)
+ *   P64 device, n-m+1 doubles (out, may be NULL): P before rounding to FP32
+ * Rows whose zone covers every window get P = +inf, I = -1.  FP32 tier only
+ * (opts may be NULL; tier must be ABJ_TIER_FP32), m <= 4096.  Errors: as
+ * ab_join, and ABJ_EINVAL if excl >= n-m+1.
+ */
+int self_join(const double* x, int64_t n, int32_t m, int64_t excl, float* P, int64_t* I, double* P64,
+              const abj_opts* opts, void* hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Learning phase (Sec. 3.1, Alg. 1): greedy choice of the windows of a
+ * training series T_B that form the dictionary D_B.
+ *
+ *   P_B <- self-join of T_B (exclusion zone m/2 rounded down), S <- 0
+ *   repeat:
+ *     P'  <- P_B - S, with +inf for every window within m/2 of an earlier
+ *            choice and for windows whose P_B is not finite
+ *     j   <- argmin P' (ties: smallest index; stop if no finite P')
+ *     add the element of j: ceil(context * m) samples centred on window j,
+ *         clipped to the series; overlapping or touching elements merge
+ *     stop when the stop condition holds (the element of this step is kept)
+ *     S'  <- distance profile of T_B against window j (Def. 4)
+ *     S   <- S' on the first step, else min(S, S')
+ *
+ * Stop conditions: ABJ_STOP_SPACE_SAVING stops once the merged dictionary
+ * holds at least (1 - stop_value) n samples; ABJ_STOP_EMAX stops once e_max
+ * of the current dictionary (Def. 10: the largest AB-join distance of a
+ * window of T_B to the dictionary, computed with the FP32 join and its FP64
+ * re-check) is <= stop_value.  max_iters > 0 caps the number of steps.
+ * ---------------------------------------------------------------------- */
+typedef enum { ABJ_STOP_SPACE_SAVING = 0, ABJ_STOP_EMAX = 1 } abj_stop;
+
+typedef struct {
+    double context;    /* element length factor k > 0: ceil(k m) samples, at least m, at most n (paper: 1.5) */
+    double stop_value; /* SPACE_SAVING: s in [0, 1]; EMAX: target >= 0 */
+    int32_t stop;      /* abj_stop */
+    int32_t max_iters; /* 0: no cap */
+} abj_learn_opts;
+
+/*
+ *   series       device, n doubles (T_B)
+ *   segments     host, 2 * max_segments int64 (out): [start, end) sample
+ *                ranges of T_B, sorted; the dictionary is their concatenation
+ *                and its seg_bounds are the running sums of their lengths
+ *   chosen       host, max_chosen int64 (out, may be NULL): the window chosen
+ *                at each step, in order
+ *   dict_out     device, n doubles (out, may be NULL): the concatenated
+ *                dictionary; n_dict receives its length
+ *   e_max        host (out, may be NULL): e_max of the final dictionary
+ *                (+inf if it is empty)
+ *   p_self       device, n-m+1 doubles (out, may be NULL): P_B
+ * Blocking: runs on hip_stream and synchronises it once per step.
+ * Errors: ABJ_EINVAL for m outside [2, 4096], n < m, bad opts, NULL required
+ * pointers or non-device buffers, and (after the run, with no output
+ * written) when the segments or choices exceed max_segments / max_chosen;
+ * ABJ_ENOMEM / ABJ_EHIP from the runtime.
+ */
+int dict_build(const double* series, int64_t n, int32_t m, const abj_learn_opts* opts, int64_t* segments,
+               int32_t max_segments, int32_t* n_segments, int64_t* chosen, int32_t max_chosen, int32_t* n_chosen,
+               double* dict_out, int64_t* n_dict, double* e_max, double* p_self, void* hip_stream);
+
 /* ------------------------------------------------------------------------
  * Resident dictionary: the learned dictionary of the inference phase (Alg. 2
  * joins every incoming series against the same D_B) kept in library-owned

@@ -37,6 +37,14 @@ class abj_opts(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+class abj_learn_opts(ctypes.Structure):
+    _fields_ = [("context", ctypes.c_double), ("stop_value", ctypes.c_double), ("stop", ctypes.c_int32),
+                ("max_iters", ctypes.c_int32)]
+
+
+STOPS = {"space_saving": 0, "e_max": 1}
+
+
 class abj_server_opts(ctypes.Structure):
     _fields_ = [("tier", ctypes.c_int32), ("max_slots", ctypes.c_int32), ("mem_budget", ctypes.c_int64),
                 ("backend", ctypes.c_int32), ("sim_n_ms", ctypes.c_int32), ("sim_ms", ctypes.c_int32 * 8),
@@ -82,6 +90,10 @@ def lib():
         L.abj_window_stats.argtypes = [_vp, _i64, _i32, _vp, _vp, _vp, _vp]
         L.ab_join.argtypes = [_vp, _i64, _vp, _i64, ctypes.POINTER(_i64), _i32, _i32, _vp, _vp,
                               ctypes.POINTER(abj_opts), _vp]
+        L.self_join.argtypes = [_vp, _i64, _i32, _i64, _vp, _vp, _vp, ctypes.POINTER(abj_opts), _vp]
+        L.dict_build.argtypes = [_vp, _i64, _i32, ctypes.POINTER(abj_learn_opts), ctypes.POINTER(_i64), _i32,
+                                 ctypes.POINTER(_i32), ctypes.POINTER(_i64), _i32, ctypes.POINTER(_i32), _vp,
+                                 ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double), _vp, _vp]
         L.abj_profile_enable.argtypes = [ctypes.c_int]
         L.abj_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
         L.abj_dict_create.argtypes = [_vp, _i64, ctypes.POINTER(_i64), _i32, ctypes.POINTER(_i32), _i32,
@@ -96,7 +108,7 @@ def lib():
         L.abj_server_drain.argtypes = [_vp, _i32]
         L.abj_server_stats_get.argtypes = [_vp, ctypes.POINTER(abj_server_stats)]
         L.abj_server_destroy.argtypes = [_vp]
-        for f in ("abj_init", "abj_window_stats", "ab_join", "abj_profile_enable", "abj_profile_read",
+        for f in ("abj_init", "abj_window_stats", "ab_join", "self_join", "dict_build", "abj_profile_enable", "abj_profile_read",
                   "abj_dict_create", "abj_dict_free", "ab_join_dict", "abj_server_create", "abj_submit", "abj_wait",
                   "abj_result", "abj_cancel", "abj_server_drain", "abj_server_stats_get", "abj_server_destroy"):
             getattr(L, f).restype = ctypes.c_int
@@ -159,6 +171,53 @@ def ab_join(query, dictionary, seg_bounds: Sequence[int], m: int, tier: str = "f
                        _stream_ptr(stream))
     _check(rc)
     return P, I
+
+
+def self_join(x, m: int, excl: int = -1, stream=None):
+    """Self-join matrix profile of ``x`` with trivial matches ``|i - j| <= excl``
+    excluded (``excl < 0``: m // 2).  Returns ``(P, I, P64)`` CUDA tensors."""
+    import torch
+
+    x = _dev_f64(x, "x")
+    W = max(x.numel() - m + 1, 0)
+    P = torch.empty(W, dtype=torch.float32, device=x.device)
+    I = torch.empty(W, dtype=torch.int64, device=x.device)
+    P64 = torch.empty(W, dtype=torch.float64, device=x.device)
+    _check(lib().self_join(x.data_ptr(), x.numel(), int(m), int(excl), P.data_ptr() if W else None,
+                           I.data_ptr() if W else None, P64.data_ptr() if W else None, None, _stream_ptr(stream)))
+    return P, I, P64
+
+
+def dict_build(series, m: int, context: float = 1.5, stop: str = "space_saving", value: float = 0.9,
+               max_iters: int = 0, stream=None):
+    """Learning phase (Alg. 1) on the GPU.
+
+    Returns a dict with ``segments`` (list of [start, end) ranges of the
+    series), ``chosen`` (windows in the order chosen), ``dictionary`` (CUDA
+    float64 tensor, the concatenated segments), ``bounds`` (its segment
+    offsets), ``orig_start`` (segment starts in the series), ``e_max`` and
+    ``p_b`` (the self-join profile, CUDA float64).
+    """
+    import torch
+
+    x = _dev_f64(series, "series")
+    n = x.numel()
+    W = max(n - m + 1, 0)
+    cap = W if max_iters <= 0 else min(W, max_iters)
+    segs = np.zeros(2 * max(cap, 1), dtype=np.int64)
+    chosen = np.zeros(max(cap, 1), dtype=np.int64)
+    d = torch.empty(max(n, 1), dtype=torch.float64, device=x.device)
+    pb = torch.empty(max(W, 1), dtype=torch.float64, device=x.device)
+    nseg, nch, nd, em = _i32(0), _i32(0), _i64(0), ctypes.c_double(0.0)
+    o = abj_learn_opts(float(context), float(value), STOPS[stop], int(max_iters))
+    _check(lib().dict_build(x.data_ptr(), n, int(m), ctypes.byref(o), segs.ctypes.data_as(ctypes.POINTER(_i64)),
+                            max(cap, 1), ctypes.byref(nseg), chosen.ctypes.data_as(ctypes.POINTER(_i64)),
+                            max(cap, 1), ctypes.byref(nch), d.data_ptr(), ctypes.byref(nd), ctypes.byref(em),
+                            pb.data_ptr() if W else None, _stream_ptr(stream)))
+    sg = [(int(segs[2 * k]), int(segs[2 * k + 1])) for k in range(nseg.value)]
+    bounds = np.concatenate([[0], np.cumsum([b - a for a, b in sg])]).astype(np.int64)
+    return dict(segments=sg, chosen=chosen[:nch.value].copy(), dictionary=d[:nd.value], bounds=bounds,
+                orig_start=np.array([a for a, _ in sg], dtype=np.int64), e_max=em.value, p_b=pb[:W])
 
 
 def window_stats(x, m: int, stream=None):

@@ -111,6 +111,7 @@ struct Fp32Slot {
     int64_t tile0;
     int64_t nbands, nchunks, tc;
     int64_t pairs;  // valid pairs (for timing records)
+    int64_t excl;   // self-join trivial-match zone: pairs with |i - j| <= excl are skipped (-1: none)
     int32_t m;
     int32_t pad;
 };
@@ -119,12 +120,16 @@ int64_t fp32_slot_tiles(const Fp32Slot& sl);
 size_t fp32_lds_bytes(int max_m);
 // FP32 diagonal join of every tile of every slot (persistent workgroups, one
 // atomic tile counter); writes one packed (score, index) key per query row.
+// self: the slots are self-joins whose excl fields are honoured.
 int join_fp32_batch(const Fp32Slot* slots_dev, int nslots, int64_t ntiles, int max_m, int64_t pairs,
-                    unsigned long long* counter_dev, hipStream_t stream);
+                    unsigned long long* counter_dev, hipStream_t stream, bool self = false);
 
-// Turns packed keys into P (FP64 re-check, flat conventions) and I.
+// Turns packed keys into P (FP64 re-check, flat conventions) and I; P64
+// (optional) receives the same distances unrounded.  excl >= 0 makes it a
+// self-join epilogue: the flat conventions then only take reference windows
+// outside |j - i| <= excl.
 int finalize_launch(const SeriesDev& A, const SeriesDev& B, const unsigned long long* keys, float* P, int64_t* I,
-                    hipStream_t stream);
+                    hipStream_t stream, double* P64 = nullptr, int64_t excl = -1);
 
 int fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t stream);
 

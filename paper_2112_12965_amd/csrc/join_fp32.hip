@@ -98,10 +98,11 @@ __device__ inline unsigned long long pack_key(float s, int j)
 // One sweep step over column j.  On entry logical row r of this lane lives in
 // register slot (r - U) mod kR; the step writes new row r over old row r-1
 // (in place, no register moves), so on exit row r lives in slot (r - U - 1).
-template <int U, bool kGuard>
+template <int U, bool kGuard, bool kExcl>
 __device__ __forceinline__ bool sweep_step(int64_t j, int64_t jend, ColPtr __restrict__ bcol, float e,
                                            float (&S)[kR], const float (&pf)[kR], const float (&pg)[kR],
-                                           float (&best)[kR], int (&bidx)[kR], vf4& prev)
+                                           float (&best)[kR], int (&bidx)[kR], vf4& prev, int64_t ibase,
+                                           int64_t excl)
 {
     if (kGuard && j >= jend) return false;
     const vf4 cur = bcol[j];
@@ -117,7 +118,13 @@ __device__ __forceinline__ bool sweep_step(int64_t j, int64_t jend, ColPtr __res
     if (cur[2] != 0.f) {
 #pragma unroll
         for (int r = 0; r < kR; ++r) {
-            const float sc = S[(r - 1 - U) & (kR - 1)] * cur[2];
+            float sc = S[(r - 1 - U) & (kR - 1)] * cur[2];
+            if (kExcl) {
+                // trivial match of the self-join: |j - i| <= excl is not a candidate
+                // (near the diagonal j - ibase is small, so 32 bits suffice)
+                const int rel = (int)(j - ibase) + (int)excl - r;
+                if ((unsigned)rel <= 2u * (unsigned)excl) sc = -INFINITY;
+            }
             const bool up = sc > best[r];
             // improvements are rare after the first columns: branch only when
             // some lane improves this row
@@ -136,20 +143,22 @@ __device__ __forceinline__ bool sweep_step(int64_t j, int64_t jend, ColPtr __res
 
 // kR consecutive steps starting at column jb; edge values e[0..kR) belong to
 // columns jb .. jb+kR-1.
-template <bool kGuard>
+template <bool kGuard, bool kExcl>
 __device__ __forceinline__ void sweep_block(int64_t jb, int64_t jend, ColPtr __restrict__ bcol,
                                             const float (&e)[kR], float (&S)[kR], const float (&pf)[kR],
                                             const float (&pg)[kR], float (&best)[kR], int (&bidx)[kR],
-                                            vf4& prev)
+                                            vf4& prev, int64_t ibase, int64_t excl)
 {
 #define ABJ_STEP(u) \
-    if (!sweep_step<u, kGuard>(jb + u, jend, bcol, e[u], S, pf, pg, best, bidx, prev)) return;
+    if (!sweep_step<u, kGuard, kExcl>(jb + u, jend, bcol, e[u], S, pf, pg, best, bidx, prev, ibase, excl)) return;
     ABJ_STEP(0) ABJ_STEP(1) ABJ_STEP(2) ABJ_STEP(3) ABJ_STEP(4) ABJ_STEP(5) ABJ_STEP(6) ABJ_STEP(7)
     ABJ_STEP(8) ABJ_STEP(9) ABJ_STEP(10) ABJ_STEP(11) ABJ_STEP(12) ABJ_STEP(13) ABJ_STEP(14) ABJ_STEP(15)
 #undef ABJ_STEP
 }
 
 // One tile: rows band * 1024 .. +1023 of slot `sl`, columns chunk * tc .. +tc-1.
+// kExcl: the tile meets the self-join's trivial-match zone.
+template <bool kExcl>
 __device__ __forceinline__ void join_tile(const Fp32Slot& sl, int64_t band, int64_t chunk, double* lds)
 {
     GDbl __restrict__ axc = (GDbl)sl.axc;
@@ -246,6 +255,8 @@ __device__ __forceinline__ void join_tile(const Fp32Slot& sl, int64_t band, int6
         if (inv != 0.f) {
 #pragma unroll
             for (int r = 0; r < kR; ++r) {
+                const int64_t dj = j0 - (ibase + r);
+                if (kExcl && dj <= sl.excl && dj >= -sl.excl) continue;
                 best[r] = S[r] * inv;
                 bidx[r] = (int)j0;
             }
@@ -265,7 +276,7 @@ __device__ __forceinline__ void join_tile(const Fp32Slot& sl, int64_t band, int6
             e[4 * q + 2] = v.z;
             e[4 * q + 3] = v.w;
         }
-        sweep_block<false>(jb, jend, bcol, e, S, pf, pg, best, bidx, prev);
+        sweep_block<false, kExcl>(jb, jend, bcol, e, S, pf, pg, best, bidx, prev, ibase, sl.excl);
     }
     {
         const int64_t jb = j0 + 1 + nfull * kR;
@@ -273,7 +284,7 @@ __device__ __forceinline__ void join_tile(const Fp32Slot& sl, int64_t band, int6
             float e[kR];
 #pragma unroll
             for (int u = 0; u < kR; ++u) e[u] = edge[nfull * kR + u];
-            sweep_block<true>(jb, jend, bcol, e, S, pf, pg, best, bidx, prev);
+            sweep_block<true, kExcl>(jb, jend, bcol, e, S, pf, pg, best, bidx, prev, ibase, sl.excl);
         }
     }
 #pragma unroll
@@ -287,6 +298,9 @@ __device__ __forceinline__ void join_tile(const Fp32Slot& sl, int64_t band, int6
 // launch's list through one atomic counter until the list is exhausted (the
 // list is finite, so every wave reaches the exit).  Tiles of different slots
 // (requests) with different lengths and window lengths share the launch.
+// kSelf: self-join launch; tiles that meet a slot's trivial-match zone take the
+// masked sweep (a separate instantiation, so the AB-join kernel carries none of it).
+template <bool kSelf>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void k_join_fp32_batch(
     const Fp32Slot* __restrict__ slots, int nslots, int64_t ntiles, unsigned long long* __restrict__ counter)
 {
@@ -311,7 +325,18 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void
         const Fp32Slot sl = slots[lo];
         const int64_t lt = (int64_t)t - sl.tile0;
         const int64_t band = lt / sl.nchunks;
-        join_tile(sl, band, lt - band * sl.nchunks, lds);
+        const int64_t chunk = lt - band * sl.nchunks;
+        if (kSelf) {
+            // does the tile meet the band |j - i| <= excl?
+            const int64_t i0 = band * kBandRows, i1 = i0 + kBandRows - 1;
+            const int64_t j0 = chunk * sl.tc, j1 = j0 + sl.tc - 1;
+            if (sl.excl >= 0 && j0 - i1 <= sl.excl && j1 - i0 >= -sl.excl)
+                join_tile<true>(sl, band, chunk, lds);
+            else
+                join_tile<false>(sl, band, chunk, lds);
+        } else {
+            join_tile<false>(sl, band, chunk, lds);
+        }
         __syncthreads();  // the next tile reuses the LDS buffers
     }
 }
@@ -340,6 +365,7 @@ void fp32_slot(const SeriesDev& A, const SeriesDev& B, unsigned long long* keys,
     sl->nchunks = nchunks;
     sl->tc = tc;
     sl->pairs = A.W * B.nvalid;
+    sl->excl = -1;
 }
 
 int64_t fp32_slot_tiles(const Fp32Slot& sl) { return sl.nbands * sl.nchunks; }
@@ -347,7 +373,7 @@ int64_t fp32_slot_tiles(const Fp32Slot& sl) { return sl.nbands * sl.nchunks; }
 size_t fp32_lds_bytes(int max_m) { return edge_offset(max_m) + sizeof(float) * (kTC + kR); }
 
 int join_fp32_batch(const Fp32Slot* slots_dev, int nslots, int64_t ntiles, int max_m, int64_t pairs,
-                    unsigned long long* counter_dev, hipStream_t stream)
+                    unsigned long long* counter_dev, hipStream_t stream, bool self)
 {
     if (ntiles <= 0) return ABJ_OK;
     ABJ_TRY(fill_u64(counter_dev, 1, 0ull, stream));
@@ -355,8 +381,12 @@ int join_fp32_batch(const Fp32Slot* slots_dev, int nslots, int64_t ntiles, int m
     const int64_t grid = ntiles < 4096 ? ntiles : 4096;
     ProfMark mark;
     ABJ_TRY(prof_begin(&mark, stream));
-    hipLaunchKernelGGL(k_join_fp32_batch, dim3((unsigned)grid), dim3(kWave), fp32_lds_bytes(max_m), stream,
-                       slots_dev, nslots, ntiles, counter_dev);
+    if (self)
+        hipLaunchKernelGGL(k_join_fp32_batch<true>, dim3((unsigned)grid), dim3(kWave), fp32_lds_bytes(max_m),
+                           stream, slots_dev, nslots, ntiles, counter_dev);
+    else
+        hipLaunchKernelGGL(k_join_fp32_batch<false>, dim3((unsigned)grid), dim3(kWave), fp32_lds_bytes(max_m),
+                           stream, slots_dev, nslots, ntiles, counter_dev);
     ABJ_HIP(hipGetLastError());
     return prof_end(&mark, stream, pairs);
 }

@@ -190,6 +190,58 @@ int dict_build(const double* series, int64_t n, int32_t m, const abj_learn_opts*
                double* dict_out, int64_t* n_dict, double* e_max, double* p_self, void* hip_stream);
 
 /* ------------------------------------------------------------------------
+ * Discords (Sec. 2: the window with the largest matrix-profile value).  For
+ * K > 1 discords the rule is greedy: the largest finite value (ties: smallest
+ * index), then every row within excl of it is dropped (|r - r*| <= excl), and
+ * so on; excl < 0 selects m - 1, so that no two discords overlap.
+ * ---------------------------------------------------------------------- */
+
+/*
+ * Greedy top-K of any profile.
+ *   P       device, W floats (NaN and +-inf rows are never chosen)
+ *   rows    host, K int64 (out)      values  host, K floats (out, may be NULL)
+ *   n_found host (out): picks made (< K when the rows run out)
+ * Blocking (synchronises hip_stream).  Errors: ABJ_EINVAL if W < 1, K < 1,
+ * excl < 0 or a pointer is NULL / not device memory.
+ */
+int topk_discords(const float* P, int64_t W, int32_t K, int64_t excl, int64_t* rows, float* values,
+                  int32_t* n_found, void* hip_stream);
+
+typedef struct {
+    int64_t rows_exact;    /* query rows joined exactly against ref */
+    int32_t rounds;        /* exact-evaluation rounds */
+    int32_t certified;     /* bit 0: largest P_hat - second largest > e_max (the paper's test);
+                              bit 1: same with the runner-up taken as the second discord, which
+                              places the exact top discord within excl of the approximate one */
+} abj_discord_info;
+
+/*
+ * Exact top-K discords of a query against a reference series (the database
+ * T_B, or several joined with seg_bounds as in ab_join), starting from the
+ * dictionary join P_hat of the same query.  By Lemmas 1 and 2 the exact
+ * profile P obeys P_hat - e_max <= P <= P_hat, so the dictionary join is an
+ * upper bound and rows far below the leaders need no exact join:
+ *   round 0: rows with P_hat >= (largest P_hat) - e_max, which hold the top
+ *            discord, are joined exactly (1024-row bands of the FP32 engine);
+ *   repeat:  greedy top-K on the mixed profile (exact where joined, P_hat
+ *            elsewhere); if every pick is exact they are the exact discords
+ *            (every other row's value is an upper bound); otherwise the bands
+ *            of all rows at or above the smallest pick value are joined.
+ *   query    device, n_query doubles       P_hat  device, n_query-m+1 floats
+ *   e_max    the dictionary's bound (Def. 10); < 0 skips round 0
+ *   ref, ref_bounds, n_ref_seg: as dict / seg_bounds / n_seg of ab_join
+ *   rows / values / neighbors: host, K entries (out): discord rows, their
+ *            exact distances, and their nearest windows in ref (values and
+ *            neighbors may be NULL)
+ *   info     host (out, may be NULL)
+ * Exact here means the FP32 tier's join (|error| <= 1e-3 against FP64).
+ * Blocking.  Errors: as ab_join for the join arguments; ABJ_EINVAL if K < 1.
+ */
+int discords(const double* query, int64_t n_query, int32_t m, const float* P_hat, double e_max, const double* ref,
+             int64_t n_ref, const int64_t* ref_bounds, int32_t n_ref_seg, int32_t K, int64_t excl, int64_t* rows,
+             float* values, int64_t* neighbors, int32_t* n_found, abj_discord_info* info, void* hip_stream);
+
+/* ------------------------------------------------------------------------
  * Resident dictionary: the learned dictionary of the inference phase (Alg. 2
  * joins every incoming series against the same D_B) kept in library-owned
  * device memory with its per-window statistics precomputed for each window

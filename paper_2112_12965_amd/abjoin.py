@@ -45,6 +45,10 @@ class abj_learn_opts(ctypes.Structure):
 STOPS = {"space_saving": 0, "e_max": 1}
 
 
+class abj_discord_info(ctypes.Structure):
+    _fields_ = [("rows_exact", ctypes.c_int64), ("rounds", ctypes.c_int32), ("certified", ctypes.c_int32)]
+
+
 class abj_server_opts(ctypes.Structure):
     _fields_ = [("tier", ctypes.c_int32), ("max_slots", ctypes.c_int32), ("mem_budget", ctypes.c_int64),
                 ("backend", ctypes.c_int32), ("sim_n_ms", ctypes.c_int32), ("sim_ms", ctypes.c_int32 * 8),
@@ -94,6 +98,11 @@ def lib():
         L.dict_build.argtypes = [_vp, _i64, _i32, ctypes.POINTER(abj_learn_opts), ctypes.POINTER(_i64), _i32,
                                  ctypes.POINTER(_i32), ctypes.POINTER(_i64), _i32, ctypes.POINTER(_i32), _vp,
                                  ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double), _vp, _vp]
+        L.topk_discords.argtypes = [_vp, _i64, _i32, _i64, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_float),
+                                    ctypes.POINTER(_i32), _vp]
+        L.discords.argtypes = [_vp, _i64, _i32, _vp, ctypes.c_double, _vp, _i64, ctypes.POINTER(_i64), _i32, _i32,
+                               _i64, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_float), ctypes.POINTER(_i64),
+                               ctypes.POINTER(_i32), ctypes.POINTER(abj_discord_info), _vp]
         L.abj_profile_enable.argtypes = [ctypes.c_int]
         L.abj_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
         L.abj_dict_create.argtypes = [_vp, _i64, ctypes.POINTER(_i64), _i32, ctypes.POINTER(_i32), _i32,
@@ -108,7 +117,8 @@ def lib():
         L.abj_server_drain.argtypes = [_vp, _i32]
         L.abj_server_stats_get.argtypes = [_vp, ctypes.POINTER(abj_server_stats)]
         L.abj_server_destroy.argtypes = [_vp]
-        for f in ("abj_init", "abj_window_stats", "ab_join", "self_join", "dict_build", "abj_profile_enable", "abj_profile_read",
+        for f in ("abj_init", "abj_window_stats", "ab_join", "self_join", "dict_build", "topk_discords", "discords",
+                  "abj_profile_enable", "abj_profile_read",
                   "abj_dict_create", "abj_dict_free", "ab_join_dict", "abj_server_create", "abj_submit", "abj_wait",
                   "abj_result", "abj_cancel", "abj_server_drain", "abj_server_stats_get", "abj_server_destroy"):
             getattr(L, f).restype = ctypes.c_int
@@ -218,6 +228,51 @@ def dict_build(series, m: int, context: float = 1.5, stop: str = "space_saving",
     bounds = np.concatenate([[0], np.cumsum([b - a for a, b in sg])]).astype(np.int64)
     return dict(segments=sg, chosen=chosen[:nch.value].copy(), dictionary=d[:nd.value], bounds=bounds,
                 orig_start=np.array([a for a, _ in sg], dtype=np.int64), e_max=em.value, p_b=pb[:W])
+
+
+def _dev_f32(x, name):
+    import torch
+
+    if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dtype != torch.float32 or not x.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float32 CUDA tensor")
+    return x
+
+
+def topk_discords(P, K: int, excl: int, stream=None):
+    """Greedy top-K discords of a profile (float32 CUDA tensor): (rows, values)."""
+    P = _dev_f32(P, "P")
+    rows = np.zeros(K, dtype=np.int64)
+    vals = np.zeros(K, dtype=np.float32)
+    n = _i32(0)
+    _check(lib().topk_discords(P.data_ptr(), P.numel(), int(K), int(excl), rows.ctypes.data_as(ctypes.POINTER(_i64)),
+                               vals.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(n),
+                               _stream_ptr(stream)))
+    return rows[:n.value].copy(), vals[:n.value].copy()
+
+
+def discords(query, P_hat, e_max: float, ref, ref_bounds, m: int, K: int, excl: int = -1, stream=None):
+    """Exact top-K discords of ``query`` against ``ref`` from the dictionary join ``P_hat``.
+
+    Returns a dict with ``rows``, ``values`` (exact distances), ``neighbors``
+    (nearest windows in ``ref``), ``rows_exact``, ``rounds`` and ``certified``.
+    """
+    q = _dev_f64(query, "query")
+    r = _dev_f64(ref, "ref")
+    Ph = _dev_f32(P_hat, "P_hat")
+    b, bp, nseg = _bounds(ref_bounds)
+    rows = np.zeros(K, dtype=np.int64)
+    vals = np.zeros(K, dtype=np.float32)
+    nn = np.zeros(K, dtype=np.int64)
+    n = _i32(0)
+    info = abj_discord_info()
+    _check(lib().discords(q.data_ptr(), q.numel(), int(m), Ph.data_ptr(), float(e_max), r.data_ptr(), r.numel(), bp,
+                          nseg, int(K), int(excl), rows.ctypes.data_as(ctypes.POINTER(_i64)),
+                          vals.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                          nn.ctypes.data_as(ctypes.POINTER(_i64)), ctypes.byref(n), ctypes.byref(info),
+                          _stream_ptr(stream)))
+    k = n.value
+    return dict(rows=rows[:k].copy(), values=vals[:k].copy(), neighbors=nn[:k].copy(), rows_exact=info.rows_exact,
+                rounds=info.rounds, certified=info.certified)
 
 
 def window_stats(x, m: int, stream=None):

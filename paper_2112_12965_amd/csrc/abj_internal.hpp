@@ -95,6 +95,26 @@ void stats_carve(Arena& a, int64_t n, int32_t m, SeriesDev* s);
 int stats_compute(const double* x, SeriesDev* s, const int64_t* seg_bounds_dev, int32_t n_seg, Arena& a,
                   hipStream_t stream);
 
+// Query rows per tile of the FP32 engine: slots whose rows start at a multiple
+// of this share the engine's tiling of the whole series.
+constexpr int64_t kFp32BandRows = 1024;
+
+// A view of rows [r0, r0 + rows) of the query statistics A, for joining or
+// finishing a subset of bands (the copy behind xc keeps its zero tail).
+inline SeriesDev rows_view(const SeriesDev& A, int64_t r0, int64_t rows)
+{
+    SeriesDev v = A;
+    v.W = rows;
+    v.n = rows + A.m - 1;
+    v.xc = A.xc + r0;
+    v.mu = A.mu + r0;
+    v.sig = A.sig + r0;
+    v.dfdg = A.dfdg + r0;
+    v.col = A.col + r0;
+    v.flags = A.flags + r0;
+    return v;
+}
+
 // One query series (a "slot") of an FP32 batch launch: its statistics, the
 // reference statistics for the same m, its key array, and its tiles
 // (nbands x nchunks, numbered from tile0 in the launch's tile list).

@@ -35,6 +35,7 @@ namespace {
 constexpr int kWave = 64;
 constexpr int kR = 16;                  // query rows per lane
 constexpr int kBandRows = kR * kWave;   // query rows per tile
+static_assert(kBandRows == kFp32BandRows, "band height is part of the engine's interface");
 constexpr int kTC = 1024;               // reference columns per tile
 constexpr int kQ = kTC / kWave;         // top-edge columns per lane
 constexpr int kDppWaveShr1 = 0x138;     // DPP control: whole-wave shift right by one lane

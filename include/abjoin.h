@@ -68,6 +68,10 @@ typedef enum {
 /* opts.flags bits */
 #define ABJ_FLAG_NO_REFINE 1 /* precision tiers: skip the FP64 re-check and report the distance implied by the
                                 best 16-bit score (to measure the tier's error before refinement) */
+#define ABJ_FLAG_PEARSON 2   /* report the Pearson correlation of the nearest window, rho = 1 - d^2 / (2m), instead
+                                of d (Sec. 2 allows either measure; the nearest window is the most correlated one).
+                                Flat conventions become rho = 1 (flat-flat) and 1/2 (flat vs non-flat); a row with no
+                                window gets -inf; NaN rows stay NaN */
 
 typedef struct {
     int32_t tier;     /* abj_tier */

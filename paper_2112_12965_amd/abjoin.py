@@ -18,6 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libabjoin.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "abjoin.h")
 
+ABJ_FLAG_NO_REFINE, ABJ_FLAG_PEARSON = 1, 2
 ABJ_OK, ABJ_EINVAL, ABJ_ENOMEM, ABJ_EHIP, ABJ_EBUSY, ABJ_ECANCELED, ABJ_ETIMEOUT, ABJ_ENOTFOUND = (
     0, -1, -2, -3, -4, -5, -6, -7)
 TIERS = {"fp32": 0, "bf16": 1, "fp16": 2}
@@ -156,13 +157,14 @@ def _bounds(seg_bounds):
 
 
 def ab_join(query, dictionary, seg_bounds: Sequence[int], m: int, tier: str = "fp32", refine_k: int = 0,
-            out: Optional[tuple] = None, stream=None):
+            out: Optional[tuple] = None, stream=None, pearson: bool = False):
     """Matrix profile of ``query`` against the windows of a concatenated dictionary.
 
     ``query``/``dictionary``: float64 CUDA tensors; ``seg_bounds``: host int64
     offsets (``[0, len(dictionary)]`` for a plain AB-join).  Returns
     ``(P, I)``: float32 distances and int64 indices (CUDA tensors), enqueued on
-    the current stream.
+    the current stream.  ``pearson``: P holds the correlation of the nearest
+    window instead of its distance.
     """
     import torch
 
@@ -175,7 +177,7 @@ def ab_join(query, dictionary, seg_bounds: Sequence[int], m: int, tier: str = "f
         I = torch.empty(W, dtype=torch.int64, device=q.device)
     else:
         P, I = out
-    o = abj_opts(TIERS[tier], int(refine_k), 0, 0)
+    o = abj_opts(TIERS[tier], int(refine_k), ABJ_FLAG_PEARSON if pearson else 0, 0)
     rc = lib().ab_join(q.data_ptr(), q.numel(), d.data_ptr(), d.numel(), bp, nseg, int(m),
                        P.data_ptr() if W else None, I.data_ptr() if W else None, ctypes.byref(o),
                        _stream_ptr(stream))
@@ -183,7 +185,7 @@ def ab_join(query, dictionary, seg_bounds: Sequence[int], m: int, tier: str = "f
     return P, I
 
 
-def self_join(x, m: int, excl: int = -1, stream=None):
+def self_join(x, m: int, excl: int = -1, stream=None, pearson: bool = False):
     """Self-join matrix profile of ``x`` with trivial matches ``|i - j| <= excl``
     excluded (``excl < 0``: m // 2).  Returns ``(P, I, P64)`` CUDA tensors."""
     import torch
@@ -193,8 +195,10 @@ def self_join(x, m: int, excl: int = -1, stream=None):
     P = torch.empty(W, dtype=torch.float32, device=x.device)
     I = torch.empty(W, dtype=torch.int64, device=x.device)
     P64 = torch.empty(W, dtype=torch.float64, device=x.device)
+    o = abj_opts(0, 0, ABJ_FLAG_PEARSON if pearson else 0, 0)
     _check(lib().self_join(x.data_ptr(), x.numel(), int(m), int(excl), P.data_ptr() if W else None,
-                           I.data_ptr() if W else None, P64.data_ptr() if W else None, None, _stream_ptr(stream)))
+                           I.data_ptr() if W else None, P64.data_ptr() if W else None, ctypes.byref(o),
+                           _stream_ptr(stream)))
     return P, I, P64
 
 
@@ -312,7 +316,7 @@ class Dictionary:
         self.n = n
         self.bounds = b
 
-    def join(self, query, m, tier="fp32", refine_k=0, no_refine=False, out=None, stream=None):
+    def join(self, query, m, tier="fp32", refine_k=0, no_refine=False, out=None, stream=None, pearson=False):
         import torch
 
         q = _dev_f64(query, "query")
@@ -322,7 +326,8 @@ class Dictionary:
             I = torch.empty(W, dtype=torch.int64, device=q.device)
         else:
             P, I = out
-        o = abj_opts(TIERS[tier], int(refine_k), 1 if no_refine else 0, 0)
+        o = abj_opts(TIERS[tier], int(refine_k),
+                     (ABJ_FLAG_NO_REFINE if no_refine else 0) | (ABJ_FLAG_PEARSON if pearson else 0), 0)
         _check(lib().ab_join_dict(self.handle, q.data_ptr(), q.numel(), int(m), P.data_ptr() if W else None,
                                   I.data_ptr() if W else None, ctypes.byref(o), _stream_ptr(stream)))
         return P, I

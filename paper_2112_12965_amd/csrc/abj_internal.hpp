@@ -145,11 +145,11 @@ int join_fp32_batch(const Fp32Slot* slots_dev, int nslots, int64_t ntiles, int m
                     unsigned long long* counter_dev, hipStream_t stream, bool self = false);
 
 // Turns packed keys into P (FP64 re-check, flat conventions) and I; P64
-// (optional) receives the same distances unrounded.  excl >= 0 makes it a
+// (optional) receives the same values unrounded.  excl >= 0 makes it a
 // self-join epilogue: the flat conventions then only take reference windows
-// outside |j - i| <= excl.
+// outside |j - i| <= excl.  pearson: report 1 - d^2 / (2m) instead of d.
 int finalize_launch(const SeriesDev& A, const SeriesDev& B, const unsigned long long* keys, float* P, int64_t* I,
-                    hipStream_t stream, double* P64 = nullptr, int64_t excl = -1);
+                    hipStream_t stream, double* P64 = nullptr, int64_t excl = -1, bool pearson = false);
 
 int fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t stream);
 
@@ -166,7 +166,8 @@ int mfma_plan(int64_t WA, int64_t WB, int32_t m, int tier, int refine_k, MfmaPla
 size_t mfma_scratch_bytes(const MfmaPlan& p);
 // Operands, matrix-core sweep, FP64 re-check of all candidates (or, with
 // refine = 0, the distance implied by the best 16-bit score), conventions.
-int join_mfma_run(const SeriesDev& A, const SeriesDev& B, const MfmaPlan& p, int refine, float* P, int64_t* I,
+int join_mfma_run(const SeriesDev& A, const SeriesDev& B, const MfmaPlan& p, int refine, int pearson, float* P,
+                  int64_t* I,
                   Arena& ar, hipStream_t stream);
 
 int ensure_device();

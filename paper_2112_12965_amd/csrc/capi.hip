@@ -143,7 +143,7 @@ int check_opts(const abj_opts* opts, abj_opts* out)
     if (o.tier != ABJ_TIER_FP32 && o.tier != ABJ_TIER_BF16 && o.tier != ABJ_TIER_FP16)
         return set_error(ABJ_EINVAL, "unknown tier %d", o.tier);
     if (o.refine_k < 0 || o.refine_k > 8) return set_error(ABJ_EINVAL, "refine_k must be in 0..8");
-    if ((o.flags & ~ABJ_FLAG_NO_REFINE) != 0 || o.reserved != 0)
+    if ((o.flags & ~(ABJ_FLAG_NO_REFINE | ABJ_FLAG_PEARSON)) != 0 || o.reserved != 0)
         return set_error(ABJ_EINVAL, "unknown opts.flags bits or nonzero opts.reserved");
     *out = o;
     return ABJ_OK;
@@ -171,13 +171,14 @@ int join_query(const double* query, int64_t n, int32_t m, const SeriesDev& B, co
     unsigned long long* counter = ar.take<unsigned long long>(1);
     ABJ_TRY(stats_compute(query, &A, nullptr, 0, ar, stream));
     if (o.tier != ABJ_TIER_FP32)
-        return join_mfma_run(A, B, plan, !(o.flags & ABJ_FLAG_NO_REFINE), P, I, ar, stream);
+        return join_mfma_run(A, B, plan, !(o.flags & ABJ_FLAG_NO_REFINE), (o.flags & ABJ_FLAG_PEARSON) != 0, P, I,
+                             ar, stream);
     ABJ_TRY(fill_u64(keys, A.W, 0ull, stream));
     Fp32Slot sl;
     fp32_slot(A, B, keys, 0, &sl);
     ABJ_HIP(hipMemcpyAsync(dslot, &sl, sizeof(sl), hipMemcpyHostToDevice, stream));
     ABJ_TRY(join_fp32_batch(dslot, 1, fp32_slot_tiles(sl), m, sl.pairs, counter, stream));
-    return finalize_launch(A, B, keys, P, I, stream);
+    return finalize_launch(A, B, keys, P, I, stream, nullptr, -1, (o.flags & ABJ_FLAG_PEARSON) != 0);
 }
 
 int stats_export(const SeriesDev& s, double* mu, double* sig, uint8_t* flags, hipStream_t stream);

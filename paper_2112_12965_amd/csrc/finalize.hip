@@ -15,6 +15,15 @@ constexpr unsigned long long kNone = ~0ull;
 constexpr int kWave = 64;
 constexpr int kRowsPerBlock = 4;  // one wave per row
 
+// Pearson correlation of a distance, rho = 1 - d^2 / (2m); no window (+inf)
+// becomes -inf, NaN stays NaN.
+__device__ inline double pearson_of(double d, int m)
+{
+    if (isnan(d)) return d;
+    if (isinf(d)) return -INFINITY;
+    return 1.0 - d * d / (2.0 * (double)m);
+}
+
 __device__ inline double wave_sum(double v)
 {
 #pragma unroll
@@ -70,7 +79,7 @@ __global__ __launch_bounds__(kWave * kRowsPerBlock) void k_finalize(
     const double* __restrict__ axc, const double* __restrict__ amu, const double* __restrict__ asig,
     const uint8_t* __restrict__ aflags, int64_t WA, const double* __restrict__ bxc, const double* __restrict__ bmu,
     const double* __restrict__ bsig, const unsigned long long* __restrict__ bfirst,
-    const uint8_t* __restrict__ bflags, int64_t WB, int m, int64_t excl,
+    const uint8_t* __restrict__ bflags, int64_t WB, int m, int64_t excl, int pearson,
     const unsigned long long* __restrict__ keys, float* __restrict__ P, int64_t* __restrict__ I,
     double* __restrict__ P64)
 {
@@ -115,6 +124,7 @@ __global__ __launch_bounds__(kWave * kRowsPerBlock) void k_finalize(
             iout = j;
         }
     }
+    if (pearson) pout = pearson_of(pout, m);
     if (lane == 0) {
         P[i] = (float)pout;
         I[i] = iout;
@@ -125,12 +135,12 @@ __global__ __launch_bounds__(kWave * kRowsPerBlock) void k_finalize(
 }  // namespace
 
 int finalize_launch(const SeriesDev& A, const SeriesDev& B, const unsigned long long* keys, float* P, int64_t* I,
-                    hipStream_t stream, double* P64, int64_t excl)
+                    hipStream_t stream, double* P64, int64_t excl, bool pearson)
 {
     if (A.W <= 0) return ABJ_OK;
     const int64_t g = (A.W + kRowsPerBlock - 1) / kRowsPerBlock;
     hipLaunchKernelGGL(k_finalize, dim3((unsigned)g), dim3(kWave * kRowsPerBlock), 0, stream, A.xc, A.mu, A.sig,
-                       A.flags, A.W, B.xc, B.mu, B.sig, B.first, B.flags, B.W, (int)A.m, excl, keys, P, I, P64);
+                       A.flags, A.W, B.xc, B.mu, B.sig, B.first, B.flags, B.W, (int)A.m, excl, pearson ? 1 : 0, keys, P, I, P64);
     ABJ_HIP(hipGetLastError());
     return ABJ_OK;
 }

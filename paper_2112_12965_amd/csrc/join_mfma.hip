@@ -323,8 +323,8 @@ __global__ __launch_bounds__(256) void k_finalize_topk(
     const double* __restrict__ axc, const double* __restrict__ amu, const double* __restrict__ asig,
     const uint8_t* __restrict__ aflags, int64_t WA, const double* __restrict__ bxc, const double* __restrict__ bmu,
     const double* __restrict__ bsig, const unsigned long long* __restrict__ bfirst, int64_t WB, int m,
-    const unsigned long long* __restrict__ cand, int ncand, int keep, int refine, float* __restrict__ P,
-    int64_t* __restrict__ I)
+    const unsigned long long* __restrict__ cand, int ncand, int keep, int refine, int pearson,
+    float* __restrict__ P, int64_t* __restrict__ I)
 {
     const int lane = threadIdx.x % kWave;
     const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
@@ -332,17 +332,17 @@ __global__ __launch_bounds__(256) void k_finalize_topk(
     const uint8_t fa = aflags[i];
     const unsigned long long ff = WB > 0 ? bfirst[0] : kNone;
     const unsigned long long fv = WB > 0 ? bfirst[1] : kNone;
-    float pout;
+    double pout;
     int64_t iout;
     if (fa & kFlagBad) {
         pout = NAN;
         iout = -1;
     } else if (fa & kFlagFlat) {
         if (ff != kNone) {
-            pout = 0.f;
+            pout = 0.0;
             iout = (int64_t)ff;
         } else if (fv != kNone) {
-            pout = (float)sqrt((double)m);
+            pout = sqrt((double)m);
             iout = (int64_t)fv;
         } else {
             pout = INFINITY;
@@ -395,11 +395,12 @@ __global__ __launch_bounds__(256) void k_finalize_topk(
                 j = (int64_t)ff;
             }
         }
-        pout = (float)d;
+        pout = d;
         iout = j;
     }
+    if (pearson) pout = isnan(pout) ? pout : isinf(pout) ? -INFINITY : 1.0 - pout * pout / (2.0 * (double)m);
     if (lane == 0) {
-        P[i] = pout;
+        P[i] = (float)pout;
         I[i] = iout;
     }
 }
@@ -495,7 +496,8 @@ size_t mfma_scratch_bytes(const MfmaPlan& p)
     return b;
 }
 
-int join_mfma_run(const SeriesDev& A, const SeriesDev& B, const MfmaPlan& p, int refine, float* P, int64_t* I,
+int join_mfma_run(const SeriesDev& A, const SeriesDev& B, const MfmaPlan& p, int refine, int pearson, float* P,
+                  int64_t* I,
                   Arena& ar, hipStream_t stream)
 {
     void* zq = ar.take<char>((size_t)p.nqblk * p.KS * kWave * 16);
@@ -526,7 +528,7 @@ int join_mfma_run(const SeriesDev& A, const SeriesDev& B, const MfmaPlan& p, int
     const int rows_per_block = 4;
     hipLaunchKernelGGL(k_finalize_topk, dim3((unsigned)((A.W + rows_per_block - 1) / rows_per_block)),
                        dim3(kWave * rows_per_block), 0, stream, A.xc, A.mu, A.sig, A.flags, A.W, B.xc, B.mu, B.sig,
-                       B.first, B.W, (int)A.m, cand, (int)(p.nchunks * p.K), p.K, refine, P, I);
+                       B.first, B.W, (int)A.m, cand, (int)(p.nchunks * p.K), p.K, refine, pearson, P, I);
     ABJ_HIP(hipGetLastError());
     return ABJ_OK;
 }

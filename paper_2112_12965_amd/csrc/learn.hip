@@ -199,7 +199,8 @@ std::vector<Seg> merge_elements(std::vector<Seg> e)
 // Self-join of the statistics T (computed with the one-segment bounds) into
 // keys -> P / I / P64.
 int self_join_launch(const SeriesDev& T, int64_t excl, unsigned long long* keys, Fp32Slot* dslot,
-                     unsigned long long* counter, float* P, int64_t* I, double* P64, hipStream_t stream)
+                     unsigned long long* counter, float* P, int64_t* I, double* P64, hipStream_t stream,
+                     bool pearson = false)
 {
     ABJ_TRY(fill_u64(keys, T.W, 0ull, stream));
     Fp32Slot sl;
@@ -207,7 +208,7 @@ int self_join_launch(const SeriesDev& T, int64_t excl, unsigned long long* keys,
     sl.excl = excl;
     ABJ_HIP(hipMemcpyAsync(dslot, &sl, sizeof(sl), hipMemcpyHostToDevice, stream));
     ABJ_TRY(join_fp32_batch(dslot, 1, fp32_slot_tiles(sl), T.m, sl.pairs, counter, stream, true));
-    return finalize_launch(T, T, keys, P, I, stream, P64, excl);
+    return finalize_launch(T, T, keys, P, I, stream, P64, excl, pearson);
 }
 
 size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
@@ -356,7 +357,8 @@ extern "C" int self_join(const double* x, int64_t n, int32_t m, int64_t excl, fl
     unsigned long long* keys = ar.take<unsigned long long>((size_t)W);
     Fp32Slot* dslot = ar.take<Fp32Slot>(1);
     unsigned long long* counter = ar.take<unsigned long long>(1);
-    return self_join_launch(T, excl, keys, dslot, counter, P, I, P64, stream);
+    const bool pearson = opts && (opts->flags & ABJ_FLAG_PEARSON);
+    return self_join_launch(T, excl, keys, dslot, counter, P, I, P64, stream, pearson);
 }
 
 extern "C" int dict_build(const double* series, int64_t n, int32_t m, const abj_learn_opts* opts,

@@ -51,6 +51,10 @@ struct SeriesDev {
     uint8_t* flags = nullptr;  // W
     double* scal = nullptr;    // device scalars: [0] mean, [1] variance, [2] finite count
     unsigned long long* first = nullptr;  // [0] first valid flat window, [1] first valid window (~0 = none)
+    // reference side: column chunks of the FP32 engine, [chunks[2c], chunks[2c+1]),
+    // each inside the valid windows of one segment (see fp32_chunks_upload)
+    const int32_t* chunks = nullptr;
+    int64_t nchunks = 0;
 };
 
 // Stream-ordered scratch arena: one hipMallocAsync block carved into aligned
@@ -127,15 +131,24 @@ struct Fp32Slot {
     const double* bmu;
     const float4* bcol;
     int64_t WB;
+    const int32_t* chunks;  // reference column chunks [c0, c1) (device)
     unsigned long long* keys;
     int64_t tile0;
-    int64_t nbands, nchunks, tc;
+    int64_t nbands, nchunks;
     int64_t pairs;  // valid pairs (for timing records)
     int64_t excl;   // self-join trivial-match zone: pairs with |i - j| <= excl are skipped (-1: none)
     int32_t m;
     int32_t pad;
 };
 void fp32_slot(const SeriesDev& A, const SeriesDev& B, unsigned long long* keys, int64_t tile0, Fp32Slot* sl);
+// Column chunks of a reference of n samples with these segments (host
+// bounds; n_seg = 0 means one segment): every valid window of a segment
+// falls in one of its chunks, chunks hold at most 1024 windows, and windows
+// that cross a segment break belong to none, so the engine never sweeps them.
+// Carves the list from `ar` and copies it to the device for B.
+size_t fp32_chunk_bytes(int32_t n_seg, int64_t n);
+int fp32_chunks_upload(const int64_t* bounds, int32_t n_seg, int64_t n, int32_t m, Arena& ar, SeriesDev* B,
+                       hipStream_t stream);
 int64_t fp32_slot_tiles(const Fp32Slot& sl);
 size_t fp32_lds_bytes(int max_m);
 // FP32 diagonal join of every tile of every slot (persistent workgroups, one

@@ -281,10 +281,12 @@ extern "C" int ab_join(const double* query, int64_t n_query, const double* dict,
     Arena ar(stream);
     ar.reserve(stats_scratch_bytes(n_dict, WB));
     ar.reserve(sizeof(int64_t) * (size_t)(n_seg + 1));
+    ar.reserve(fp32_chunk_bytes(n_seg, n_dict));
     ar.reserve(query_scratch_bytes(n_query, m, WB, o, plan));
     ABJ_TRY(ar.commit());
     SeriesDev B;
     stats_carve(ar, n_dict, m, &B);
+    ABJ_TRY(fp32_chunks_upload(seg_bounds, n_seg, n_dict, m, ar, &B, stream));
     for (int32_t sgi = 0; sgi < n_seg; ++sgi) {
         const int64_t len = seg_bounds[sgi + 1] - seg_bounds[sgi];
         if (len >= m) B.nvalid += len - m + 1;

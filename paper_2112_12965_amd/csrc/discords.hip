@@ -172,6 +172,7 @@ extern "C" int discords(const double* query, int64_t n_query, int32_t m, const f
     Arena ar(stream);
     ar.reserve(stats_scratch_bytes(n_ref, WB));
     ar.reserve(sizeof(int64_t) * (size_t)(n_ref_seg + 1));
+    ar.reserve(fp32_chunk_bytes(n_ref_seg, n_ref));
     ar.reserve(stats_scratch_bytes(n_query, W));
     ar.reserve(sizeof(unsigned long long) * (size_t)W);  // keys
     ar.reserve(sizeof(float) * (size_t)W);               // mixed profile
@@ -184,6 +185,7 @@ extern "C" int discords(const double* query, int64_t n_query, int32_t m, const f
     ABJ_TRY(ar.commit());
     SeriesDev B, A;
     stats_carve(ar, n_ref, m, &B);
+    ABJ_TRY(fp32_chunks_upload(ref_bounds, n_ref_seg, n_ref, m, ar, &B, stream));
     for (int32_t s = 0; s < n_ref_seg; ++s) {
         const int64_t len = ref_bounds[s + 1] - ref_bounds[s];
         if (len >= m) B.nvalid += len - m + 1;

@@ -1,7 +1,9 @@
-// Row epilogue of the FP32 join: unpack each row's winning column, recompute
-// its distance in FP64 from the windows themselves (the norm of the difference
-// of the z-normalised windows, one wave per row, so there is no 1 - rho
-// cancellation), and apply the flat / non-finite conventions.
+// Row epilogue of the FP32 join: unpack each row's winning group of 16
+// columns, pick the column with the largest correlation among them in FP64
+// (one wave per 4 rows, one lane per row and candidate), recompute its
+// distance from the windows themselves (the norm of the difference of the
+// z-normalised windows, so there is no 1 - rho cancellation), and apply the
+// flat / non-finite conventions.
 #include <math.h>
 
 #include "abj_internal.hpp"
@@ -13,7 +15,7 @@ namespace {
 constexpr unsigned long long kNone = ~0ull;
 
 constexpr int kWave = 64;
-constexpr int kRowsPerBlock = 4;  // one wave per row
+constexpr int kWavesPerBlock = 4;
 
 // Pearson correlation of a distance, rho = 1 - d^2 / (2m); no window (+inf)
 // becomes -inf, NaN stays NaN.
@@ -24,27 +26,18 @@ __device__ inline double pearson_of(double d, int m)
     return 1.0 - d * d / (2.0 * (double)m);
 }
 
-__device__ inline double wave_sum(double v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
-}
-
-// Exact FP64 distance of two non-flat windows given their means and
-// deviations: the norm of the difference of the z-normalised windows (no
-// 1 - rho cancellation), summed across the wave.
-__device__ inline double wave_dist(const double* __restrict__ a, double ma, double sa, const double* __restrict__ b,
-                                   double mb, double sb, int m, int lane)
-{
-    const double ia = 1.0 / sa, ib = 1.0 / sb;
-    double acc = 0.0;
-    for (int k = lane; k < m; k += kWave) {
-        const double e = (a[k] - ma) * ia - (b[k] - mb) * ib;
-        acc = fma(e, e, acc);
-    }
-    return sqrt(wave_sum(acc));
-}
+constexpr int kGroup = 16;                    // columns per candidate group of the FP32 engine
+constexpr int kRowsPerWave = kWave / kGroup;  // 16 lanes per row
+constexpr int kKC = 256;                      // window samples staged per pass
+constexpr int kSlice = kKC / kGroup;          // samples per lane and pass
+constexpr int kHalf = 8;                      // samples per lane and sub-pass
+constexpr int kBLen = kKC + kGroup - 1;       // reference samples of one row's group per pass
+// LDS index of a staged sample: one pad word per 16 keeps the lanes'
+// slices (16 samples apart) on distinct banks
+__device__ __forceinline__ int pad(int t) { return t + (t >> 4); }
+constexpr int kAPad = kKC + (kKC >> 4) + 1;
+constexpr int kBPad = kBLen + (kBLen >> 4) + 1;
+constexpr int kStage = kRowsPerWave * (kAPad + kBPad);  // floats per wave
 
 // First reference window at or after `from` that is valid and, when
 // `want_flat`, flat; kNone if there is none.  Wave-wide scan, 64 columns a step.
@@ -75,7 +68,7 @@ __device__ inline unsigned long long outside_zone(unsigned long long first, cons
     return wave_find(bflags, WB, i + excl + 1, want_flat, lane);
 }
 
-__global__ __launch_bounds__(kWave * kRowsPerBlock) void k_finalize(
+__global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_finalize(
     const double* __restrict__ axc, const double* __restrict__ amu, const double* __restrict__ asig,
     const uint8_t* __restrict__ aflags, int64_t WA, const double* __restrict__ bxc, const double* __restrict__ bmu,
     const double* __restrict__ bsig, const unsigned long long* __restrict__ bfirst,
@@ -83,52 +76,219 @@ __global__ __launch_bounds__(kWave * kRowsPerBlock) void k_finalize(
     const unsigned long long* __restrict__ keys, float* __restrict__ P, int64_t* __restrict__ I,
     double* __restrict__ P64)
 {
-    const int lane = threadIdx.x % kWave;
-    const int64_t i = (int64_t)blockIdx.x * kRowsPerBlock + threadIdx.x / kWave;
-    if (i >= WA) return;  // uniform per wave
-    const uint8_t fa = aflags[i];
-    double pout = NAN;
-    int64_t iout = -1;
-    if (!(fa & kFlagBad)) {
-        // first valid flat / first valid reference window (outside the row's
-        // trivial-match zone in a self-join)
-        const unsigned long long ff = WB > 0 ? outside_zone(bfirst[0], bflags, WB, i, excl, true, lane) : kNone;
-        if (fa & kFlagFlat) {
-            const unsigned long long fv =
-                WB > 0 ? outside_zone(bfirst[1], bflags, WB, i, excl, false, lane) : kNone;
-            if (ff != kNone) {
-                pout = 0.0;
-                iout = (int64_t)ff;
-            } else if (fv != kNone) {
-                pout = sqrt((double)m);
-                iout = (int64_t)fv;
-            } else {
-                pout = INFINITY;
-            }
-        } else {
-            const unsigned long long key = keys ? keys[i] : 0ull;
-            double d = INFINITY;
-            int64_t j = -1;
-            if (key != 0ull) {
-                j = (int64_t)(0xFFFFFFFFu - (unsigned)(key & 0xFFFFFFFFull));
-                d = wave_dist(axc + i, amu[i], asig[i], bxc + j, bmu[j], bsig[j], m, lane);
-            }
-            if (ff != kNone) {
-                const double sm = sqrt((double)m);
-                if (sm < d || (sm == d && (int64_t)ff < j)) {
-                    d = sm;
-                    j = (int64_t)ff;
-                }
-            }
-            pout = d;
-            iout = j;
+    __shared__ float stage_all[kWavesPerBlock][kStage];
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    const int64_t row0 = ((int64_t)blockIdx.x * kWavesPerBlock + wave) * kRowsPerWave;
+    float* __restrict__ sa = stage_all[wave];                              // per row: its centred window
+    float* __restrict__ sb = stage_all[wave] + kRowsPerWave * kAPad;       // per row: its group's span
+
+    // ---- lanes 16 r .. 16 r + 15 serve row row0 + r; lane c scores column
+    // jb + c of the row's winning group ----
+    const int r = lane / kGroup, c = lane % kGroup;
+    const int64_t i = row0 + r;
+    uint8_t fa = kFlagBad;
+    int64_t jb = -1;
+    if (i < WA) {
+        fa = aflags[i];
+        if (keys && !(fa & (kFlagBad | kFlagFlat))) {
+            const unsigned long long key = keys[i];
+            if (key) jb = (int64_t)(0xFFFFFFFFu - (unsigned)(key & 0xFFFFFFFFull));
         }
     }
-    if (pearson) pout = pearson_of(pout, m);
-    if (lane == 0) {
-        P[i] = (float)pout;
-        I[i] = iout;
-        if (P64) P64[i] = pout;
+    // statistics of the lane's candidate, loaded while the windows stream in
+    const int64_t j = jb + c;
+    const bool cand = jb >= 0 && j < WB && (excl < 0 || j - i > excl || i - j > excl);
+    uint8_t fj = 1;
+    double mbj = 0.0, sbj = 1.0;
+    if (cand) {
+        fj = bflags[j];
+        mbj = bmu[j];
+        sbj = bsig[j];
+    }
+    const double mai = i < WA ? amu[i] : 0.0, sai = i < WA ? asig[i] : 1.0;
+    const double mb0 = jb >= 0 ? bmu[jb] : 0.0;
+    int64_t jrows[kRowsPerWave];
+    double mas[kRowsPerWave], mbs[kRowsPerWave];
+#pragma unroll
+    for (int rr = 0; rr < kRowsPerWave; ++rr) {
+        jrows[rr] = __shfl(jb, rr * kGroup, kWave);
+        mas[rr] = __shfl(mai, rr * kGroup, kWave);
+        mbs[rr] = __shfl(mb0, rr * kGroup, kWave);
+    }
+    const bool any = jrows[0] >= 0 || jrows[1] >= 0 || jrows[2] >= 0 || jrows[3] >= 0;
+
+    // ---- choosing the column: FP32 dots of the row's window minus its mean
+    // with the group's span minus the first candidate's mean (the candidates'
+    // means differ by little, and the window minus its mean sums to zero, so
+    // the dots are the covariances up to rounding); each pass stages 256
+    // samples per row in LDS and lane c dots its 16 with the 16 shifted spans
+    // through a sliding register window ----
+    float acc[kGroup];
+#pragma unroll
+    for (int v = 0; v < kGroup; ++v) acc[v] = 0.f;
+    // every wave of the block runs the same passes (m is uniform), so all of
+    // them reach the barriers
+    for (int kc = 0; kc < m; kc += kKC) {
+        const int len = m - kc < kKC ? m - kc : kKC;
+        if (any) {
+#pragma unroll
+            for (int rr = 0; rr < kRowsPerWave; ++rr) {
+                const int64_t jr = jrows[rr];
+                float va[kKC / kWave], vb[(kBLen + kWave - 1) / kWave];
+#pragma unroll
+                for (int x = 0; x < kKC / kWave; ++x) {
+                    const int t = lane + x * kWave;
+                    va[x] = (jr >= 0 && t < len) ? (float)(axc[row0 + rr + kc + t] - mas[rr]) : 0.f;
+                }
+#pragma unroll
+                for (int x = 0; x < (kBLen + kWave - 1) / kWave; ++x) {
+                    const int t = lane + x * kWave;
+                    // < n + 15: inside the padded copy
+                    vb[x] = (jr >= 0 && t < len + kGroup - 1) ? (float)(bxc[jr + kc + t] - mbs[rr]) : 0.f;
+                }
+#pragma unroll
+                for (int x = 0; x < kKC / kWave; ++x) sa[rr * kAPad + pad(lane + x * kWave)] = va[x];
+#pragma unroll
+                for (int x = 0; x < (kBLen + kWave - 1) / kWave; ++x) {
+                    const int t = lane + x * kWave;
+                    if (t < kBLen) sb[rr * kBPad + pad(t)] = vb[x];
+                }
+            }
+        }
+        __syncthreads();
+        if (jb >= 0) {
+            const float* __restrict__ ra = sa + r * kAPad;
+            const float* __restrict__ rb = sb + r * kBPad;
+#pragma unroll
+            for (int h = 0; h < kSlice; h += kHalf) {
+                const int t0 = c * kSlice + h;
+                if (t0 < len) {
+                    float av[kHalf], w[kHalf + kGroup - 1];
+#pragma unroll
+                    for (int u = 0; u < kHalf; ++u) av[u] = ra[pad(t0 + u)];
+#pragma unroll
+                    for (int x = 0; x < kHalf + kGroup - 1; ++x) w[x] = rb[pad(t0 + x)];
+#pragma unroll
+                    for (int u = 0; u < kHalf; ++u)
+#pragma unroll
+                        for (int x = 0; x < kGroup; ++x) acc[x] = fmaf(av[u], w[u + x], acc[x]);
+                }
+            }
+        }
+        if (kc + kKC < m) __syncthreads();  // the next pass overwrites the stage
+    }
+    // halving exchange within the row's 16 lanes: after it lane c holds the
+    // sum of column 8 bit3 + 4 bit2 + 2 bit1 + bit0 of c, which is c
+    float h8[8], h4[4], h2[2], dot;
+#pragma unroll
+    for (int x = 0; x < 8; ++x) {
+        const bool hi = c & 8;
+        h8[x] = (hi ? acc[x + 8] : acc[x]) + __shfl_xor(hi ? acc[x] : acc[x + 8], 8, kWave);
+    }
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+        const bool hi = c & 4;
+        h4[x] = (hi ? h8[x + 4] : h8[x]) + __shfl_xor(hi ? h8[x] : h8[x + 4], 4, kWave);
+    }
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+        const bool hi = c & 2;
+        h2[x] = (hi ? h4[x + 2] : h4[x]) + __shfl_xor(hi ? h4[x] : h4[x + 2], 2, kWave);
+    }
+    {
+        const bool hi = c & 1;
+        dot = (hi ? h2[1] : h2[0]) + __shfl_xor(hi ? h2[0] : h2[1], 1, kWave);
+    }
+    double score = -INFINITY;
+    if (cand && fj == 0) score = (double)dot / sbj;
+    // best column of the row (ties -> smaller column)
+    int cb = c;
+#pragma unroll
+    for (int off = 1; off < kGroup; off <<= 1) {
+        const double os = __shfl_xor(score, off, kWave);
+        const int oc = __shfl_xor(cb, off, kWave);
+        if (os > score || (os == score && oc < cb)) {
+            score = os;
+            cb = oc;
+        }
+    }
+    const int64_t jbest = score == -INFINITY ? -1 : jb + cb;
+    // its exact distance in FP64, the norm of the difference of the
+    // z-normalised windows, split over the row's 16 lanes
+    const double mb = __shfl(mbj, r * kGroup + cb, kWave), sbb = __shfl(sbj, r * kGroup + cb, kWave);
+    double sq = 0.0;
+    if (jbest >= 0) {
+        const double ia = 1.0 / sai, ib = 1.0 / sbb;
+        double s2[4] = {0.0, 0.0, 0.0, 0.0};
+        int k = c;
+        // four independent sums, loads of eight samples in flight
+        for (; k + 7 * kGroup < m; k += 8 * kGroup) {
+            double av[8], bv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                av[u] = axc[i + k + u * kGroup];
+                bv[u] = bxc[jbest + k + u * kGroup];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const double e = (av[u] - mai) * ia - (bv[u] - mb) * ib;
+                s2[u & 3] = fma(e, e, s2[u & 3]);
+            }
+        }
+        for (; k < m; k += kGroup) {
+            const double e = (axc[i + k] - mai) * ia - (bxc[jbest + k] - mb) * ib;
+            s2[0] = fma(e, e, s2[0]);
+        }
+        sq = (s2[0] + s2[1]) + (s2[2] + s2[3]);
+    }
+#pragma unroll
+    for (int off = 1; off < kGroup; off <<= 1) sq += __shfl_xor(sq, off, kWave);
+    const double dist = jbest >= 0 ? sqrt(sq) : INFINITY;
+
+    // ---- conventions: the flat rows and the flat reference rule, one row at
+    // a time (the self-join's zone scans use the whole wave) ----
+    const unsigned long long ff0 = WB > 0 ? bfirst[0] : kNone, fv0 = WB > 0 ? bfirst[1] : kNone;
+    for (int rr = 0; rr < kRowsPerWave; ++rr) {
+        const int64_t ii = row0 + rr;
+        if (ii >= WA) break;
+        const uint8_t fr = (uint8_t)__shfl((int)fa, rr * kGroup, kWave);
+        double pout = NAN;
+        int64_t iout = -1;
+        if (!(fr & kFlagBad)) {
+            // first valid flat / first valid reference window (outside the
+            // row's trivial-match zone in a self-join)
+            const unsigned long long ff = outside_zone(ff0, bflags, WB, ii, excl, true, lane);
+            if (fr & kFlagFlat) {
+                const unsigned long long fv = outside_zone(fv0, bflags, WB, ii, excl, false, lane);
+                if (ff != kNone) {
+                    pout = 0.0;
+                    iout = (int64_t)ff;
+                } else if (fv != kNone) {
+                    pout = sqrt((double)m);
+                    iout = (int64_t)fv;
+                } else {
+                    pout = INFINITY;
+                }
+            } else {
+                double d = __shfl(dist, rr * kGroup, kWave);
+                int64_t jj = __shfl(jbest, rr * kGroup, kWave);
+                if (ff != kNone) {
+                    const double sm = sqrt((double)m);
+                    if (sm < d || (sm == d && (int64_t)ff < jj)) {
+                        d = sm;
+                        jj = (int64_t)ff;
+                    }
+                }
+                pout = d;
+                iout = jj;
+            }
+        }
+        if (pearson) pout = pearson_of(pout, m);
+        if (lane == 0) {
+            P[ii] = (float)pout;
+            I[ii] = iout;
+            if (P64) P64[ii] = pout;
+        }
     }
 }
 
@@ -138,8 +298,9 @@ int finalize_launch(const SeriesDev& A, const SeriesDev& B, const unsigned long 
                     hipStream_t stream, double* P64, int64_t excl, bool pearson)
 {
     if (A.W <= 0) return ABJ_OK;
-    const int64_t g = (A.W + kRowsPerBlock - 1) / kRowsPerBlock;
-    hipLaunchKernelGGL(k_finalize, dim3((unsigned)g), dim3(kWave * kRowsPerBlock), 0, stream, A.xc, A.mu, A.sig,
+    const int64_t rows_per_block = (int64_t)kWavesPerBlock * kRowsPerWave;
+    const int64_t g = (A.W + rows_per_block - 1) / rows_per_block;
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)g), dim3(kWave * kWavesPerBlock), 0, stream, A.xc, A.mu, A.sig,
                        A.flags, A.W, B.xc, B.mu, B.sig, B.first, B.flags, B.W, (int)A.m, excl, pearson ? 1 : 0, keys, P, I, P64);
     ABJ_HIP(hipGetLastError());
     return ABJ_OK;

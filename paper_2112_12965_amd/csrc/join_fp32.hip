@@ -10,21 +10,28 @@
 //   cov(i+1, j+1) = cov(i, j) + df_a(i) dg_b(j) + df_b(j) dg_a(i).
 //
 // Work decomposition (one 64-lane wave per tile, no inter-wave traffic):
-//   * a tile is 1024 query rows x 1024 reference columns;
-//   * lane l owns rows i0 + 16 l .. i0 + 16 l + 15 and keeps their covariance,
-//     running best score and best column in registers;
-//   * the wave walks the tile's columns in order; a column's terms
-//     {df_b, dg_b, 1/sigma_b} are the same for all lanes, so they come from
-//     scalar loads;
+//   * a tile is 1024 query rows x one chunk of at most 1024 reference columns;
+//     chunks come from a host-made list and lie inside one segment's valid
+//     windows, so windows that cross a segment break are never swept;
+//   * lane l owns rows i0 + 16 l .. i0 + 16 l + 15 and keeps their covariance
+//     and running best score in registers;
+//   * the wave walks the chunk's columns in order; a column's terms
+//     {df_b, dg_b, 1/sigma_b, bias} are the same for all lanes, so they come
+//     from scalar loads (bias = -inf for flat or non-finite windows);
 //   * cov(i, j) needs cov(i-1, j-1): for a lane's first row that is the last
 //     row of the lane below, moved across with one DPP wave_shr:1; lane 0 takes
 //     the tile's top edge instead;
 //   * the tile's left column and top row are exact FP64 dot products (so FP32
-//     drift is bounded by the tile size); columns excluded by the segment mask
-//     or the flat rule skip the scoring but still advance the recurrence;
-//   * at the end each row's best (score, column) is merged across tiles with a
-//     64-bit atomic max on an order-preserving key (ties -> smallest column).
+//     drift is bounded by the tile size);
+//   * scores are folded with a max per row within each group of 16 columns and
+//     only the group is recorded, so the sweep has no data-dependent branch;
+//   * at the end each row's best (score, group) is merged across tiles with a
+//     64-bit atomic max on an order-preserving key (ties -> first group), and
+//     the epilogue picks the row's column within the group in FP64.
 #include <math.h>
+
+#include <algorithm>
+#include <vector>
 
 #include "abj_internal.hpp"
 
@@ -96,14 +103,31 @@ __device__ inline unsigned long long pack_key(float s, int j)
     return ((unsigned long long)u << 32) | (unsigned long long)(0xFFFFFFFFu - (unsigned)j);
 }
 
+// Score of logical row r at column j after the step that wrote it (slot
+// (r - 1 - U) mod kR): cov / sigma_j plus the column's bias (0, or -inf for a
+// reference window that cannot match), and -inf for a self-join trivial match.
+template <int U, bool kExcl>
+__device__ __forceinline__ float step_score(const float (&S)[kR], int r, const vf4& cur, int64_t j, int64_t ibase,
+                                            int64_t excl)
+{
+    float sc = fmaf(S[(r - 1 - U) & (kR - 1)], cur[2], cur[3]);
+    if (kExcl) {
+        // |j - i| <= excl is not a candidate (near the diagonal j - ibase is
+        // small, so 32 bits suffice)
+        const int rel = (int)(j - ibase) + (int)excl - r;
+        if ((unsigned)rel <= 2u * (unsigned)excl) sc = -INFINITY;
+    }
+    return sc;
+}
+
 // One sweep step over column j.  On entry logical row r of this lane lives in
 // register slot (r - U) mod kR; the step writes new row r over old row r-1
 // (in place, no register moves), so on exit row r lives in slot (r - U - 1).
+// blk[r] keeps the best score of row r over the steps of the current block.
 template <int U, bool kGuard, bool kExcl>
 __device__ __forceinline__ bool sweep_step(int64_t j, int64_t jend, ColPtr __restrict__ bcol, float e,
                                            float (&S)[kR], const float (&pf)[kR], const float (&pg)[kR],
-                                           float (&best)[kR], int (&bidx)[kR], vf4& prev, int64_t ibase,
-                                           int64_t excl)
+                                           float (&blk)[kR], vf4& prev, int64_t ibase, int64_t excl)
 {
     if (kGuard && j >= jend) return false;
     const vf4 cur = bcol[j];
@@ -116,48 +140,42 @@ __device__ __forceinline__ bool sweep_step(int64_t j, int64_t jend, ColPtr __res
         c = fmaf(pg[r], prev[0], fmaf(pf[r], prev[1], c));
     }
     S[(kR - 1 - U) & (kR - 1)] = fmaf(pg[0], prev[0], fmaf(pf[0], prev[1], t));
-    if (cur[2] != 0.f) {
 #pragma unroll
-        for (int r = 0; r < kR; ++r) {
-            float sc = S[(r - 1 - U) & (kR - 1)] * cur[2];
-            if (kExcl) {
-                // trivial match of the self-join: |j - i| <= excl is not a candidate
-                // (near the diagonal j - ibase is small, so 32 bits suffice)
-                const int rel = (int)(j - ibase) + (int)excl - r;
-                if ((unsigned)rel <= 2u * (unsigned)excl) sc = -INFINITY;
-            }
-            const bool up = sc > best[r];
-            // improvements are rare after the first columns: branch only when
-            // some lane improves this row
-            if (__builtin_expect(__builtin_amdgcn_ballot_w64(up) != 0, 0)) {
-                // keeps this a real branch: without it the compiler turns the
-                // update into unconditional selects on every step
-                asm volatile("" ::: "memory");
-                best[r] = up ? sc : best[r];
-                bidx[r] = up ? (int)j : bidx[r];
-            }
-        }
+    for (int r = 0; r < kR; ++r) {
+        const float sc = step_score<U, kExcl>(S, r, cur, j, ibase, excl);
+        blk[r] = U == 0 ? sc : fmaxf(blk[r], sc);
     }
     prev = cur;
     return true;
 }
 
-// kR consecutive steps starting at column jb; edge values e[0..kR) belong to
-// columns jb .. jb+kR-1.
+// kR consecutive steps starting at column jb (edge values e[0..kR) belong to
+// columns jb .. jb+kR-1), then one update per row: if the block's best score
+// beats the row's best, the row remembers the block (the first such block on
+// ties).  The epilogue finds the winning column among the block's kR columns
+// in FP64, so the sweep itself carries no per-column index and no branch.
 template <bool kGuard, bool kExcl>
 __device__ __forceinline__ void sweep_block(int64_t jb, int64_t jend, ColPtr __restrict__ bcol,
                                             const float (&e)[kR], float (&S)[kR], const float (&pf)[kR],
                                             const float (&pg)[kR], float (&best)[kR], int (&bidx)[kR],
                                             vf4& prev, int64_t ibase, int64_t excl)
 {
+    float blk[kR];
 #define ABJ_STEP(u) \
-    if (!sweep_step<u, kGuard, kExcl>(jb + u, jend, bcol, e[u], S, pf, pg, best, bidx, prev, ibase, excl)) return;
+    if (!sweep_step<u, kGuard, kExcl>(jb + u, jend, bcol, e[u], S, pf, pg, blk, prev, ibase, excl)) goto done;
     ABJ_STEP(0) ABJ_STEP(1) ABJ_STEP(2) ABJ_STEP(3) ABJ_STEP(4) ABJ_STEP(5) ABJ_STEP(6) ABJ_STEP(7)
     ABJ_STEP(8) ABJ_STEP(9) ABJ_STEP(10) ABJ_STEP(11) ABJ_STEP(12) ABJ_STEP(13) ABJ_STEP(14) ABJ_STEP(15)
 #undef ABJ_STEP
+done:
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+        const bool up = blk[r] > best[r];
+        best[r] = up ? blk[r] : best[r];
+        bidx[r] = up ? (int)jb : bidx[r];
+    }
 }
 
-// One tile: rows band * 1024 .. +1023 of slot `sl`, columns chunk * tc .. +tc-1.
+// One tile: rows band * 1024 .. +1023 of slot `sl`, the columns of one chunk.
 // kExcl: the tile meets the self-join's trivial-match zone.
 template <bool kExcl>
 __device__ __forceinline__ void join_tile(const Fp32Slot& sl, int64_t band, int64_t chunk, double* lds)
@@ -171,7 +189,6 @@ __device__ __forceinline__ void join_tile(const Fp32Slot& sl, int64_t band, int6
     unsigned long long* __restrict__ keys = sl.keys;
     const int64_t WA = sl.WA, WB = sl.WB;
     const int m = sl.m;
-    const int64_t tc = sl.tc;
 
     double* wv = lds;                                  // m doubles: one centred window
     // kTC + kR floats, 16-byte aligned: edge[t] = cov(i0, j0 + 1 + t)
@@ -179,8 +196,9 @@ __device__ __forceinline__ void join_tile(const Fp32Slot& sl, int64_t band, int6
 
     const int lane = threadIdx.x;
     const int64_t i0 = band * kBandRows;
-    const int64_t j0 = chunk * tc;  // tc <= kTC columns per tile, chosen by the host to balance tiles
-    const int64_t jend = j0 + tc < WB ? j0 + tc : WB;
+    const int32_t __attribute__((address_space(4)))* ch = (const int32_t __attribute__((address_space(4)))*)sl.chunks;
+    const int64_t j0 = ch[2 * chunk];    // at most kTC columns, all valid (host-made list)
+    const int64_t jend = ch[2 * chunk + 1];
     const int64_t ibase = i0 + (int64_t)lane * kR;
 
     // ---- top edge: cov(i0, j) for the tile's columns ------------------------
@@ -197,6 +215,7 @@ __device__ __forceinline__ void join_tile(const Fp32Slot& sl, int64_t band, int6
         const int64_t cbase = j0 + (int64_t)lane * kQ;
 #pragma unroll
         for (int h = 0; h < kQ; h += kG) {
+            if (cbase + h >= jend) break;  // columns past the chunk are never swept
             double acc[kG];
             sliding_dots<kG>(bxc, cbase + h, wv, m, acc);
 #pragma unroll
@@ -252,15 +271,15 @@ __device__ __forceinline__ void join_tile(const Fp32Slot& sl, int64_t band, int6
         bidx[r] = -1;
     }
     {
-        const float inv = bcol[j0][2];
-        if (inv != 0.f) {
+        // column j0 opens the first candidate group [j0, j0 + kR)
+        const vf4 c0 = bcol[j0];
 #pragma unroll
-            for (int r = 0; r < kR; ++r) {
-                const int64_t dj = j0 - (ibase + r);
-                if (kExcl && dj <= sl.excl && dj >= -sl.excl) continue;
-                best[r] = S[r] * inv;
-                bidx[r] = (int)j0;
-            }
+        for (int r = 0; r < kR; ++r) {
+            float sc = fmaf(S[r], c0[2], c0[3]);
+            const int64_t dj = j0 - (ibase + r);
+            if (kExcl && dj <= sl.excl && dj >= -sl.excl) sc = -INFINITY;
+            best[r] = sc;
+            bidx[r] = (int)j0;
         }
     }
     vf4 prev = bcol[j0];
@@ -291,7 +310,7 @@ __device__ __forceinline__ void join_tile(const Fp32Slot& sl, int64_t band, int6
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
         const int64_t i = ibase + r;
-        if (i < WA && bidx[r] >= 0) atomicMax(&keys[i], pack_key(best[r], bidx[r]));
+        if (i < WA && best[r] > -INFINITY) atomicMax(&keys[i], pack_key(best[r], bidx[r]));
     }
 }
 
@@ -330,7 +349,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void
         if (kSelf) {
             // does the tile meet the band |j - i| <= excl?
             const int64_t i0 = band * kBandRows, i1 = i0 + kBandRows - 1;
-            const int64_t j0 = chunk * sl.tc, j1 = j0 + sl.tc - 1;
+            const int64_t j0 = sl.chunks[2 * chunk], j1 = sl.chunks[2 * chunk + 1] - 1;
             if (sl.excl >= 0 && j0 - i1 <= sl.excl && j1 - i0 >= -sl.excl)
                 join_tile<true>(sl, band, chunk, lds);
             else
@@ -358,18 +377,49 @@ void fp32_slot(const SeriesDev& A, const SeriesDev& B, unsigned long long* keys,
     sl->keys = keys;
     sl->tile0 = tile0;
     sl->nbands = A.W > 0 ? (A.W + kBandRows - 1) / kBandRows : 0;
-    int64_t nchunks = B.W > 0 ? (B.W + kTC - 1) / kTC : 0;
-    // equal chunk widths (multiple of 16) so that no tile is a sliver
-    int64_t tc = nchunks > 0 ? (B.W + nchunks - 1) / nchunks : kTC;
-    tc = (tc + kR - 1) / kR * kR;
-    if (tc > kTC) tc = kTC;
-    sl->nchunks = nchunks;
-    sl->tc = tc;
+    sl->chunks = B.chunks;
+    sl->nchunks = B.W > 0 ? B.nchunks : 0;
     sl->pairs = A.W * B.nvalid;
     sl->excl = -1;
 }
 
 int64_t fp32_slot_tiles(const Fp32Slot& sl) { return sl.nbands * sl.nchunks; }
+
+size_t fp32_chunk_bytes(int32_t n_seg, int64_t n)
+{
+    const int64_t most = n / kTC + (n_seg > 0 ? n_seg : 1) + 1;
+    return (sizeof(int32_t) * 2 * (size_t)most + 255) & ~size_t(255);
+}
+
+int fp32_chunks_upload(const int64_t* bounds, int32_t n_seg, int64_t n, int32_t m, Arena& ar, SeriesDev* B,
+                       hipStream_t stream)
+{
+    std::vector<int32_t> c;
+    auto split = [&](int64_t a, int64_t cnt) {
+        // equal widths, a multiple of 16 except the last, so that no tile is a sliver
+        const int64_t k = (cnt + kTC - 1) / kTC;
+        int64_t w = (cnt + k - 1) / k;
+        w = std::min<int64_t>((w + kR - 1) / kR * kR, kTC);
+        for (int64_t s = 0; s < cnt; s += w) {
+            c.push_back((int32_t)(a + s));
+            c.push_back((int32_t)(a + std::min(cnt, s + w)));
+        }
+    };
+    if (n_seg <= 0) {
+        if (n >= m) split(0, n - m + 1);
+    } else {
+        for (int32_t s = 0; s < n_seg; ++s) {
+            const int64_t len = bounds[s + 1] - bounds[s];
+            if (len >= m) split(bounds[s], len - m + 1);
+        }
+    }
+    int32_t* d = ar.take<int32_t>(c.size() > 0 ? c.size() : 1);
+    B->chunks = d;
+    B->nchunks = (int64_t)c.size() / 2;
+    if (!c.empty())
+        ABJ_HIP(hipMemcpyAsync(d, c.data(), sizeof(int32_t) * c.size(), hipMemcpyHostToDevice, stream));
+    return ABJ_OK;
+}
 
 size_t fp32_lds_bytes(int max_m) { return edge_offset(max_m) + sizeof(float) * (kTC + kR); }
 

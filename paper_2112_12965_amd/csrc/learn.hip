@@ -228,6 +228,7 @@ int check_self_args(const double* x, int64_t n, int32_t m, const abj_opts* opts)
 int series_stats(const double* x, int64_t n, int32_t m, Arena& ar, SeriesDev* T, hipStream_t stream)
 {
     stats_carve(ar, n, m, T);
+    ABJ_TRY(fp32_chunks_upload(nullptr, 0, n, m, ar, T, stream));
     T->nvalid = T->W;
     int64_t* db = ar.take<int64_t>(2);
     const int64_t hb[2] = {0, n};
@@ -235,7 +236,10 @@ int series_stats(const double* x, int64_t n, int32_t m, Arena& ar, SeriesDev* T,
     return stats_compute(x, T, db, 1, ar, stream);
 }
 
-size_t series_stats_bytes(int64_t n, int64_t W) { return stats_scratch_bytes(n, W) + al256(2 * sizeof(int64_t)); }
+size_t series_stats_bytes(int64_t n, int64_t W)
+{
+    return stats_scratch_bytes(n, W) + al256(2 * sizeof(int64_t)) + fp32_chunk_bytes(0, n);
+}
 
 // State of one dict_build call.
 struct Learner {
@@ -294,6 +298,7 @@ int e_max_of(Learner& L, const std::vector<Seg>& segs, double* out)
     Arena ar(L.dict_ws, L.dict_ws_bytes);
     SeriesDev B;
     stats_carve(ar, nd, L.m, &B);
+    ABJ_TRY(fp32_chunks_upload(hb, nseg, nd, L.m, ar, &B, L.stream));
     for (const Seg& s : segs)
         if (s.b - s.a >= L.m) B.nvalid += s.b - s.a - L.m + 1;
     ABJ_TRY(stats_compute(L.dict, &B, L.dbounds, nseg, ar, L.stream));
@@ -400,7 +405,7 @@ extern "C" int dict_build(const double* series, int64_t n, int32_t m, const abj_
     L.m = m;
     const int64_t Lmin = std::max<int64_t>(m, std::min<int64_t>(n, (int64_t)ceil(o.context * (double)m)));
     L.max_dseg = n / (Lmin + 1) + 1;  // merged segments are disjoint and do not touch
-    L.dict_ws_bytes = stats_scratch_bytes(n, W) + 256;
+    L.dict_ws_bytes = stats_scratch_bytes(n, W) + fp32_chunk_bytes((int32_t)std::min<int64_t>(L.max_dseg, INT32_MAX), n) + 256;
     Arena ar(stream);
     ar.reserve(series_stats_bytes(n, W));
     ar.reserve(sizeof(unsigned long long) * (size_t)W);  // keys

@@ -115,13 +115,15 @@ extern "C" int abj_dict_create(const double* dict, int64_t n_dict, const int64_t
             DictM e;
             e.m = ms[a];
             const int64_t W = n_dict >= e.m ? n_dict - e.m + 1 : 0;
-            const size_t bytes = stats_scratch_bytes(n_dict, W);
+            const size_t bytes = stats_scratch_bytes(n_dict, W) + fp32_chunk_bytes(n_seg, n_dict);
             if (hipMalloc(&e.mem, bytes) != hipSuccess) {
                 rc = set_error(ABJ_ENOMEM, "dictionary statistics allocation failed");
                 break;
             }
             Arena ar(e.mem, bytes);
             stats_carve(ar, n_dict, e.m, &e.B);
+            rc = fp32_chunks_upload(seg_bounds, n_seg, n_dict, e.m, ar, &e.B, st);
+            if (rc != ABJ_OK) break;
             for (int32_t sgi = 0; sgi < n_seg; ++sgi) {
                 const int64_t len = seg_bounds[sgi + 1] - seg_bounds[sgi];
                 if (len >= e.m) e.B.nvalid += len - e.m + 1;

@@ -373,7 +373,8 @@ __global__ __launch_bounds__(kThreads) void k_window_stats(
     }
     dfdg[i] = make_float2(df, dg);
     const bool usable = f == 0;
-    col[i] = make_float4(df, dg, usable ? (float)(1.0 / sd) : 0.f, 0.f);
+    // bias -inf: the window never wins a row (the FP32 engine adds it to every score)
+    col[i] = make_float4(df, dg, usable ? (float)(1.0 / sd) : 0.f, usable ? 0.f : -INFINITY);
     if (first && !(f & (kFlagBad | kFlagInvalid))) {
         atomicMin(&first[1], (unsigned long long)i);
         if (f & kFlagFlat) atomicMin(&first[0], (unsigned long long)i);

@@ -41,6 +41,7 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kR = 16;                  // query rows per lane
+constexpr int kB = 16;                  // columns per sweep block (= candidate group of the epilogue)
 constexpr int kBandRows = kR * kWave;   // query rows per tile
 static_assert(kBandRows == kFp32BandRows, "band height is part of the engine's interface");
 constexpr int kTC = 1024;               // reference columns per tile
@@ -149,14 +150,14 @@ __device__ __forceinline__ bool sweep_step(int64_t j, int64_t jend, ColPtr __res
     return true;
 }
 
-// kR consecutive steps starting at column jb (edge values e[0..kR) belong to
-// columns jb .. jb+kR-1), then one update per row: if the block's best score
+// kB consecutive steps starting at column jb (edge values e[0..kB) belong to
+// columns jb .. jb+kB-1), then one update per row: if the block's best score
 // beats the row's best, the row remembers the block (the first such block on
-// ties).  The epilogue finds the winning column among the block's kR columns
+// ties).  The epilogue finds the winning column among the block's kB columns
 // in FP64, so the sweep itself carries no per-column index and no branch.
 template <bool kGuard, bool kExcl>
 __device__ __forceinline__ void sweep_block(int64_t jb, int64_t jend, ColPtr __restrict__ bcol,
-                                            const float (&e)[kR], float (&S)[kR], const float (&pf)[kR],
+                                            const float (&e)[kB], float (&S)[kR], const float (&pf)[kR],
                                             const float (&pg)[kR], float (&best)[kR], int (&bidx)[kR],
                                             vf4& prev, int64_t ibase, int64_t excl)
 {
@@ -191,7 +192,7 @@ __device__ __forceinline__ void join_tile(const Fp32Slot& sl, int64_t band, int6
     const int m = sl.m;
 
     double* wv = lds;                                  // m doubles: one centred window
-    // kTC + kR floats, 16-byte aligned: edge[t] = cov(i0, j0 + 1 + t)
+    // kTC + kB floats, 16-byte aligned: edge[t] = cov(i0, j0 + 1 + t)
     float* edge = reinterpret_cast<float*>(reinterpret_cast<char*>(lds) + edge_offset(m));
 
     const int lane = threadIdx.x;
@@ -271,7 +272,7 @@ __device__ __forceinline__ void join_tile(const Fp32Slot& sl, int64_t band, int6
         bidx[r] = -1;
     }
     {
-        // column j0 opens the first candidate group [j0, j0 + kR)
+        // column j0 opens the first candidate group [j0, j0 + kB)
         const vf4 c0 = bcol[j0];
 #pragma unroll
         for (int r = 0; r < kR; ++r) {
@@ -283,13 +284,13 @@ __device__ __forceinline__ void join_tile(const Fp32Slot& sl, int64_t band, int6
         }
     }
     vf4 prev = bcol[j0];
-    const int64_t nfull = (jend - j0 - 1) / kR;  // full 16-column blocks after column j0
+    const int64_t nfull = (jend - j0 - 1) / kB;  // full blocks after column j0
     for (int64_t b = 0; b < nfull; ++b) {
-        const int64_t jb = j0 + 1 + b * kR;
-        float e[kR];
-        const float4* e4 = reinterpret_cast<const float4*>(edge + b * kR);
+        const int64_t jb = j0 + 1 + b * kB;
+        float e[kB];
+        const float4* e4 = reinterpret_cast<const float4*>(edge + b * kB);
 #pragma unroll
-        for (int q = 0; q < kR / 4; ++q) {
+        for (int q = 0; q < kB / 4; ++q) {
             const float4 v = e4[q];
             e[4 * q] = v.x;
             e[4 * q + 1] = v.y;
@@ -299,11 +300,11 @@ __device__ __forceinline__ void join_tile(const Fp32Slot& sl, int64_t band, int6
         sweep_block<false, kExcl>(jb, jend, bcol, e, S, pf, pg, best, bidx, prev, ibase, sl.excl);
     }
     {
-        const int64_t jb = j0 + 1 + nfull * kR;
+        const int64_t jb = j0 + 1 + nfull * kB;
         if (jb < jend) {
-            float e[kR];
+            float e[kB];
 #pragma unroll
-            for (int u = 0; u < kR; ++u) e[u] = edge[nfull * kR + u];
+            for (int u = 0; u < kB; ++u) e[u] = edge[nfull * kB + u];
             sweep_block<true, kExcl>(jb, jend, bcol, e, S, pf, pg, best, bidx, prev, ibase, sl.excl);
         }
     }
@@ -399,7 +400,7 @@ int fp32_chunks_upload(const int64_t* bounds, int32_t n_seg, int64_t n, int32_t 
         // equal widths, a multiple of 16 except the last, so that no tile is a sliver
         const int64_t k = (cnt + kTC - 1) / kTC;
         int64_t w = (cnt + k - 1) / k;
-        w = std::min<int64_t>((w + kR - 1) / kR * kR, kTC);
+        w = std::min<int64_t>((w + kB - 1) / kB * kB, kTC);
         for (int64_t s = 0; s < cnt; s += w) {
             c.push_back((int32_t)(a + s));
             c.push_back((int32_t)(a + std::min(cnt, s + w)));
@@ -421,7 +422,7 @@ int fp32_chunks_upload(const int64_t* bounds, int32_t n_seg, int64_t n, int32_t 
     return ABJ_OK;
 }
 
-size_t fp32_lds_bytes(int max_m) { return edge_offset(max_m) + sizeof(float) * (kTC + kR); }
+size_t fp32_lds_bytes(int max_m) { return edge_offset(max_m) + sizeof(float) * (kTC + kB); }
 
 int join_fp32_batch(const Fp32Slot* slots_dev, int nslots, int64_t ntiles, int max_m, int64_t pairs,
                     unsigned long long* counter_dev, hipStream_t stream, bool self)

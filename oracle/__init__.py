@@ -14,8 +14,8 @@ Each function follows a definition or algorithm of the paper (see the header of
 * ``ab_join``       -- Def. 7 matrix profile over the Def. 8 windows (Alg. 2)
 * ``pair_dists``    -- Def. 4 z-normalised Euclidean distance for given pairs
 * ``dist_matrix``   -- every pairwise distance (tiny inputs only)
-* ``self_join``     -- Alg. 1 line 3, intra-similarity join with exclusion zone
-* ``dist_profile``  -- Def. 4 distance profile (Alg. 1 line 15)
+* ``self_join``     -- Alg. 1's self-join (P_B), intra-similarity join with exclusion zone
+* ``dist_profile``  -- Def. 4 distance profile (Alg. 1's profile of the chosen window)
 * ``learn_dictionary`` (in ``oracle.learn``) -- Alg. 1
 """
 from __future__ import annotations

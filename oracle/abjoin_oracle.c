@@ -36,7 +36,7 @@
  *     windows; on the query side the row gets P = NaN, I = -1.
  *   - Ties: the smallest reference index wins (strict '<' in index order).
  *   - No exclusion zone in the AB-join.  The self-join used by the learning
- *     phase (Alg. 1 line 3) excludes |i - j| <= floor(m/2).
+ *     phase (Alg. 1's P_B) excludes |i - j| <= floor(m/2).
  *
  * All arithmetic is IEEE double; the build uses -O2 without fast-math.
  */
@@ -303,7 +303,7 @@ int orc_dist_matrix(const double* q, int64_t nq, const double* d, int64_t nd, in
 }
 
 /*
- * Self-join matrix profile (the intra-similarity join of Alg. 1 line 3): for
+ * Self-join matrix profile (the intra-similarity join that gives Alg. 1's P_B): for
  * every window i of x, the nearest other window j with |i - j| > excl.
  */
 int orc_self_join(const double* x, int64_t n, int32_t m, int64_t excl,
@@ -342,7 +342,7 @@ int orc_self_join(const double* x, int64_t n, int32_t m, int64_t excl,
 /*
  * Distance profile (Def. 4): the distance between the length-m query w and
  * every window of x.  The flat test for w uses the variance of x's samples,
- * since w is one of x's subsequences in Alg. 1 line 15.
+ * since w is one of x's subsequences in Alg. 1.
  */
 int orc_dist_profile(const double* x, int64_t n, int32_t m, const double* w, double* S)
 {

@@ -1,19 +1,16 @@
 """Oracle of the learning phase (Alg. 1, LearnDictionary) -- TEST INFRASTRUCTURE ONLY.
 
-Plain Python over the FP64 primitives of this package, in the order of the
-paper's listing:
+Plain Python over the FP64 primitives of this package, taking the steps of
+the greedy loop in the paper's order:
 
-  P_B  <- self-join of T_B                                   (Alg. 1 line 3)
-  S    <- 0, D <- {}                                         (lines 4-5)
+  P_B <- self-join of T_B (trivial matches excluded); S <- 0; D <- {}
   loop:
-    P'  <- P_B - S                                           (line 7)
-    P'[i] <- inf for |i - s| <= floor(m/2), s = start of every
-             window already chosen                           (lines 8-10)
-    j   <- argmin P'                                         (line 11)
-    add T_B[j:j+m] with context to D                         (line 12)
-    stop if the terminal condition holds                     (lines 13-14)
-    S'  <- distance profile of T_B against T_B[j:j+m]        (line 15)
-    S   <- S' if this is the first element, else min(S, S')  (lines 16-19)
+    P'  <- P_B - S, and +inf within floor(m/2) of every window already chosen
+    j   <- argmin P'
+    add T_B[j:j+m] with its context to D
+    stop if the terminal condition holds
+    S'  <- distance profile of T_B against T_B[j:j+m]
+    S   <- S' for the first element, else min(S, S')
 
 Readings where the paper leaves a choice (listed in the design notes):
   * context: the element is ceil(k m) samples (k = 1.5 in the paper), centred on

@@ -450,7 +450,7 @@ extern "C" int dict_build(const double* series, int64_t n, int32_t m, const abj_
     L.dbounds = ar.take<int64_t>((size_t)(2 * L.max_dseg + 1));
     L.dict_ws = ar.take<char>(L.dict_ws_bytes);
 
-    // ---- P_B: self-join with the m/2 zone (Alg. 1 line 3) ----
+    // ---- P_B: self-join of T_B with the m/2 zone (Alg. 1) ----
     const int64_t excl = m / 2;
     ABJ_TRY(self_join_launch(L.ts, excl, L.keys, L.slot, L.counter, L.P, L.I, L.PB, stream));
     ABJ_HIP(hipMemsetAsync(L.S, 0, sizeof(double) * (size_t)W, stream));

@@ -312,7 +312,7 @@ def test_invalid_arguments(orc):
 
 # ---------------------------------------------------------------- learning-phase primitives
 def test_self_join_matches_scipy_with_exclusion(orc):
-    """Alg. 1 line 3: intra-join with trivial-match exclusion |i - j| <= floor(m/2)."""
+    """Alg. 1's P_B: intra-join with trivial-match exclusion |i - j| <= floor(m/2)."""
     rng = np.random.default_rng(31)
     for m in (4, 9, 32):
         x = rng.standard_normal(400).cumsum()

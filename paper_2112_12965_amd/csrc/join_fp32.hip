@@ -47,7 +47,7 @@ static_assert(kBandRows == kFp32BandRows, "band height is part of the engine's i
 constexpr int kTC = 1024;               // reference columns per tile
 constexpr int kQ = kTC / kWave;         // top-edge columns per lane
 constexpr int kDppWaveShr1 = 0x138;     // DPP control: whole-wave shift right by one lane
-constexpr int kG = 8;                   // width of the FP64 edge dot-product groups
+constexpr int kG = 16;                  // width of the FP64 edge dot-product groups
 
 // acc[g] = sum_{k<m} w[k] * x[base + g + k] for g < G.  x is read through a
 // G-entry register window that slides by one sample per k (one load per G FMAs).

@@ -145,17 +145,20 @@ void fp32_slot(const SeriesDev& A, const SeriesDev& B, unsigned long long* keys,
 // bounds; n_seg = 0 means one segment): every valid window of a segment
 // falls in one of its chunks, chunks hold at most 1024 windows, and windows
 // that cross a segment break belong to none, so the engine never sweeps them.
-// Carves the list from `ar` and copies it to the device for B.
+// Carves the list from `ar` and copies it to the device for B; with dbounds
+// the same copy also brings the segment bounds (*dbounds points at them).
 size_t fp32_chunk_bytes(int32_t n_seg, int64_t n);
 int fp32_chunks_upload(const int64_t* bounds, int32_t n_seg, int64_t n, int32_t m, Arena& ar, SeriesDev* B,
-                       hipStream_t stream);
+                       hipStream_t stream, int64_t** dbounds = nullptr);
 int64_t fp32_slot_tiles(const Fp32Slot& sl);
 size_t fp32_lds_bytes(int max_m);
 // FP32 diagonal join of every tile of every slot (persistent workgroups, one
-// atomic tile counter); writes one packed (score, index) key per query row.
+// atomic tile counter); writes one packed (score, group) key per query row.
 // self: the slots are self-joins whose excl fields are honoured.
+// counter_zeroed: the caller already cleared the tile counter on the stream.
 int join_fp32_batch(const Fp32Slot* slots_dev, int nslots, int64_t ntiles, int max_m, int64_t pairs,
-                    unsigned long long* counter_dev, hipStream_t stream, bool self = false);
+                    unsigned long long* counter_dev, hipStream_t stream, bool self = false,
+                    bool counter_zeroed = false);
 
 // Turns packed keys into P (FP64 re-check, flat conventions) and I; P64
 // (optional) receives the same values unrounded.  excl >= 0 makes it a

@@ -155,8 +155,8 @@ size_t query_scratch_bytes(int64_t n, int32_t m, int64_t WB, const abj_opts& o, 
     const int64_t W = n - m + 1;
     size_t b = stats_scratch_bytes(n, W);
     b += (sizeof(unsigned long long) * (size_t)W + 255) & ~size_t(255);
-    b += 256;  // slot descriptor
     b += 256;  // tile counter
+    b += 256;  // slot descriptor
     if (o.tier != ABJ_TIER_FP32) b += mfma_scratch_bytes(plan);
     return b;
 }
@@ -166,18 +166,20 @@ int join_query(const double* query, int64_t n, int32_t m, const SeriesDev& B, co
 {
     SeriesDev A;
     stats_carve(ar, n, m, &A);
+    // keys and the tile counter are adjacent pieces: one fill clears both
+    const size_t key_words = ((sizeof(unsigned long long) * (size_t)A.W + 255) & ~size_t(255)) / 8;
     unsigned long long* keys = ar.take<unsigned long long>((size_t)A.W);
-    Fp32Slot* dslot = ar.take<Fp32Slot>(1);
     unsigned long long* counter = ar.take<unsigned long long>(1);
+    Fp32Slot* dslot = ar.take<Fp32Slot>(1);
     ABJ_TRY(stats_compute(query, &A, nullptr, 0, ar, stream));
     if (o.tier != ABJ_TIER_FP32)
         return join_mfma_run(A, B, plan, !(o.flags & ABJ_FLAG_NO_REFINE), (o.flags & ABJ_FLAG_PEARSON) != 0, P, I,
                              ar, stream);
-    ABJ_TRY(fill_u64(keys, A.W, 0ull, stream));
+    ABJ_TRY(fill_u64(keys, (int64_t)key_words + 1, 0ull, stream));
     Fp32Slot sl;
     fp32_slot(A, B, keys, 0, &sl);
     ABJ_HIP(hipMemcpyAsync(dslot, &sl, sizeof(sl), hipMemcpyHostToDevice, stream));
-    ABJ_TRY(join_fp32_batch(dslot, 1, fp32_slot_tiles(sl), m, sl.pairs, counter, stream));
+    ABJ_TRY(join_fp32_batch(dslot, 1, fp32_slot_tiles(sl), m, sl.pairs, counter, stream, false, true));
     return finalize_launch(A, B, keys, P, I, stream, nullptr, -1, (o.flags & ABJ_FLAG_PEARSON) != 0);
 }
 
@@ -280,19 +282,17 @@ extern "C" int ab_join(const double* query, int64_t n_query, const double* dict,
     hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
     Arena ar(stream);
     ar.reserve(stats_scratch_bytes(n_dict, WB));
-    ar.reserve(sizeof(int64_t) * (size_t)(n_seg + 1));
-    ar.reserve(fp32_chunk_bytes(n_seg, n_dict));
+    ar.reserve(fp32_chunk_bytes(n_seg, n_dict));  // chunk list and segment bounds
     ar.reserve(query_scratch_bytes(n_query, m, WB, o, plan));
     ABJ_TRY(ar.commit());
     SeriesDev B;
     stats_carve(ar, n_dict, m, &B);
-    ABJ_TRY(fp32_chunks_upload(seg_bounds, n_seg, n_dict, m, ar, &B, stream));
+    int64_t* dbounds = nullptr;
+    ABJ_TRY(fp32_chunks_upload(seg_bounds, n_seg, n_dict, m, ar, &B, stream, &dbounds));
     for (int32_t sgi = 0; sgi < n_seg; ++sgi) {
         const int64_t len = seg_bounds[sgi + 1] - seg_bounds[sgi];
         if (len >= m) B.nvalid += len - m + 1;
     }
-    int64_t* dbounds = ar.take<int64_t>((size_t)(n_seg + 1));
-    ABJ_HIP(hipMemcpyAsync(dbounds, seg_bounds, sizeof(int64_t) * (size_t)(n_seg + 1), hipMemcpyHostToDevice, stream));
     ABJ_TRY(stats_compute(dict, &B, dbounds, n_seg, ar, stream));
     return join_query(query, n_query, m, B, o, plan, P_AB, I_AB, ar, stream);
 }

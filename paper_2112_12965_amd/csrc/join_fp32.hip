@@ -29,6 +29,7 @@
 //     64-bit atomic max on an order-preserving key (ties -> first group), and
 //     the epilogue picks the row's column within the group in FP64.
 #include <math.h>
+#include <string.h>
 
 #include <algorithm>
 #include <vector>
@@ -389,11 +390,12 @@ int64_t fp32_slot_tiles(const Fp32Slot& sl) { return sl.nbands * sl.nchunks; }
 size_t fp32_chunk_bytes(int32_t n_seg, int64_t n)
 {
     const int64_t most = n / kTC + (n_seg > 0 ? n_seg : 1) + 1;
-    return (sizeof(int32_t) * 2 * (size_t)most + 255) & ~size_t(255);
+    const size_t bounds = sizeof(int64_t) * (size_t)((n_seg > 0 ? n_seg : 0) + 1);
+    return (bounds + sizeof(int32_t) * 2 * (size_t)most + 255) & ~size_t(255);
 }
 
 int fp32_chunks_upload(const int64_t* bounds, int32_t n_seg, int64_t n, int32_t m, Arena& ar, SeriesDev* B,
-                       hipStream_t stream)
+                       hipStream_t stream, int64_t** dbounds)
 {
     std::vector<int32_t> c;
     auto split = [&](int64_t a, int64_t cnt) {
@@ -414,21 +416,27 @@ int fp32_chunks_upload(const int64_t* bounds, int32_t n_seg, int64_t n, int32_t 
             if (len >= m) split(bounds[s], len - m + 1);
         }
     }
-    int32_t* d = ar.take<int32_t>(c.size() > 0 ? c.size() : 1);
-    B->chunks = d;
+    // one copy: the segment bounds (when asked for), then the chunk list
+    const size_t nb = (dbounds && n_seg > 0) ? (size_t)(n_seg + 1) : 0;
+    std::vector<int64_t> buf(nb + (c.size() + 1) / 2, 0);
+    if (nb) memcpy(buf.data(), bounds, sizeof(int64_t) * nb);
+    if (!c.empty()) memcpy(buf.data() + nb, c.data(), sizeof(int32_t) * c.size());
+    int64_t* d = ar.take<int64_t>(buf.size() > 0 ? buf.size() : 1);
+    if (dbounds) *dbounds = nb ? d : nullptr;
+    B->chunks = reinterpret_cast<int32_t*>(d + nb);
     B->nchunks = (int64_t)c.size() / 2;
-    if (!c.empty())
-        ABJ_HIP(hipMemcpyAsync(d, c.data(), sizeof(int32_t) * c.size(), hipMemcpyHostToDevice, stream));
+    if (!buf.empty())
+        ABJ_HIP(hipMemcpyAsync(d, buf.data(), sizeof(int64_t) * buf.size(), hipMemcpyHostToDevice, stream));
     return ABJ_OK;
 }
 
 size_t fp32_lds_bytes(int max_m) { return edge_offset(max_m) + sizeof(float) * (kTC + kB); }
 
 int join_fp32_batch(const Fp32Slot* slots_dev, int nslots, int64_t ntiles, int max_m, int64_t pairs,
-                    unsigned long long* counter_dev, hipStream_t stream, bool self)
+                    unsigned long long* counter_dev, hipStream_t stream, bool self, bool counter_zeroed)
 {
     if (ntiles <= 0) return ABJ_OK;
-    ABJ_TRY(fill_u64(counter_dev, 1, 0ull, stream));
+    if (!counter_zeroed) ABJ_TRY(fill_u64(counter_dev, 1, 0ull, stream));
     // enough one-wave workgroups to fill every SIMD four deep, never more than tiles
     const int64_t grid = ntiles < 4096 ? ntiles : 4096;
     ProfMark mark;

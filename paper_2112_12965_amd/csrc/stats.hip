@@ -1,12 +1,14 @@
 // Per-window statistics on the GPU: the O(n) step before the pair loop.
 //
 // The z-normalised distance (Def. 4) needs each window's mean and population
-// deviation.  They come from FP64 prefix sums of the series minus its global
-// mean.  The running sums are kept as double-double pairs (error-free
-// TwoSum accumulation, squares split exactly with an FMA): on a long random
-// walk the plain running sum of squares reaches ~1e12 and a window difference
-// would otherwise lose ~1e-4 absolute, which is enough to misjudge short,
-// nearly constant windows.  The same pass produces the
+// deviation.  They come from prefix sums of the series kept as double-double
+// pairs (error-free TwoSum accumulation, squares split exactly with an FMA):
+// on a long random walk the plain running sum of squares reaches ~1e12 and a
+// window difference would otherwise lose ~1e-4 absolute, which is enough to
+// misjudge short, nearly constant windows; with ~106 bits the window variance
+// m var = sum x^2 - (sum x)^2 / m keeps full FP64 precision without centring
+// the series first.  Four launches: block sums, top scan (also the series
+// variance for the flat test), local scan, per-window pass.  The same pass produces the
 // per-window terms of the diagonal covariance recurrence used by the FP32 join:
 //   df(i) = (x[i+m] - x[i]) / 2,
 //   dg(i) = (x[i+m] - mu(i+1)) + (x[i] - mu(i)),
@@ -28,7 +30,6 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kPerThread = 8;
 constexpr int kBlockElems = kThreads * kPerThread;  // 2048 samples per scan block
-constexpr int kSumBlocks = 512;                     // blocks of the mean reduction
 
 __device__ inline bool finite_d(double v) { return isfinite(v); }
 
@@ -85,24 +86,7 @@ __device__ inline dd dd_div(dd a, double b)
     return two_sum(q1, q2);
 }
 
-// Block-wide exclusive scan of one double per thread (Hillis-Steele in LDS).
-__device__ inline double block_excl_scan(double v, double* sh, double* total)
-{
-    const int t = threadIdx.x;
-    sh[t] = v;
-    __syncthreads();
-    for (int off = 1; off < kThreads; off <<= 1) {
-        double add = t >= off ? sh[t - off] : 0.0;
-        __syncthreads();
-        sh[t] += add;
-        __syncthreads();
-    }
-    double incl = sh[t];
-    if (total) *total = sh[kThreads - 1];
-    __syncthreads();
-    return incl - v;
-}
-
+// Block-wide exclusive scans (Hillis-Steele in LDS).
 __device__ inline dd block_excl_scan_dd(dd v, double* shh, double* shl, dd* total)
 {
     const int t = threadIdx.x;
@@ -141,64 +125,15 @@ __device__ inline long long block_excl_scan_i(long long v, long long* sh, long l
     return incl - v;
 }
 
-// Pass 1: per-block sum and count of the finite samples (fixed grid, so the
-// reduction order and hence the mean are deterministic for a given n).
-__global__ __launch_bounds__(kThreads) void k_partial_sums(const double* __restrict__ x, int64_t n,
-                                                           double* __restrict__ psum, long long* __restrict__ pcnt)
-{
-    __shared__ double sh[kThreads];
-    __shared__ long long shc[kThreads];
-    double s = 0.0;
-    long long c = 0;
-    for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < n; t += (int64_t)gridDim.x * kThreads) {
-        double v = x[t];
-        if (finite_d(v)) {
-            s += v;
-            ++c;
-        }
-    }
-    double tot;
-    long long totc;
-    block_excl_scan(s, sh, &tot);
-    block_excl_scan_i(c, shc, &totc);
-    if (threadIdx.x == 0) {
-        psum[blockIdx.x] = tot;
-        pcnt[blockIdx.x] = totc;
-    }
-}
-
-// Pass 1b: mean of the finite samples -> scal[0]; count -> scal[2].
-__global__ __launch_bounds__(kThreads) void k_mean(const double* __restrict__ psum, const long long* __restrict__ pcnt,
-                                                   int nparts, double* __restrict__ scal)
-{
-    __shared__ double sh[kThreads];
-    __shared__ long long shc[kThreads];
-    double s = 0.0;
-    long long c = 0;
-    for (int p = threadIdx.x; p < nparts; p += kThreads) {
-        s += psum[p];
-        c += pcnt[p];
-    }
-    double tot;
-    long long totc;
-    block_excl_scan(s, sh, &tot);
-    block_excl_scan_i(c, shc, &totc);
-    if (threadIdx.x == 0) {
-        scal[0] = totc > 0 ? tot / (double)totc : 0.0;
-        scal[2] = (double)totc;
-    }
-}
-
-// Pass 2: centred copy xc = x - mean (non-finite -> 0) and per-block sums of
-// xc, xc^2 (double-double) and the non-finite count.
+// Pass 1: the working copy xc (non-finite -> 0, zero tail of kSeriesPad
+// samples) and per-block sums of xc, xc^2 (double-double) and the
+// non-finite count.
 __global__ __launch_bounds__(kThreads) void k_block_sums(const double* __restrict__ x, int64_t n,
-                                                         const double* __restrict__ scal, double* __restrict__ xc,
-                                                         dd* __restrict__ b1, dd* __restrict__ b2,
-                                                         long long* __restrict__ bnf)
+                                                         double* __restrict__ xc, dd* __restrict__ b1,
+                                                         dd* __restrict__ b2, long long* __restrict__ bnf)
 {
     __shared__ double shh[kThreads], shl[kThreads];
     __shared__ long long shc[kThreads];
-    const double c = scal[0];
     const int64_t base = (int64_t)blockIdx.x * kBlockElems + (int64_t)threadIdx.x * kPerThread;
     dd s1 = {0.0, 0.0}, s2 = {0.0, 0.0};
     long long nf = 0;
@@ -209,13 +144,15 @@ __global__ __launch_bounds__(kThreads) void k_block_sums(const double* __restric
             double v = x[t];
             double d = 0.0;
             if (finite_d(v)) {
-                d = v - c;
+                d = v;
             } else {
                 ++nf;
             }
             xc[t] = d;
             s1 = dd_add(s1, {d, 0.0});
             s2 = dd_add(s2, dd_sqr(d));
+        } else if (t < n + kSeriesPad) {
+            xc[t] = 0.0;
         }
     }
     dd t1, t2;
@@ -230,11 +167,13 @@ __global__ __launch_bounds__(kThreads) void k_block_sums(const double* __restric
     }
 }
 
-// Pass 3: exclusive scan of the block sums (one workgroup), and the series
-// variance about its mean -> scal[1].
+// Pass 2: exclusive scan of the block sums (one workgroup); the series'
+// finite count -> scal[2], variance about its mean -> scal[1] (scal[0] = 0:
+// the working copy is not shifted); first[] reset for the per-window pass.
 __global__ __launch_bounds__(kThreads) void k_scan_top(dd* __restrict__ b1, dd* __restrict__ b2,
-                                                       long long* __restrict__ bnf, int64_t nb,
-                                                       double* __restrict__ scal)
+                                                       long long* __restrict__ bnf, int64_t nb, int64_t n,
+                                                       double* __restrict__ scal,
+                                                       unsigned long long* __restrict__ first)
 {
     __shared__ double shh[kThreads], shl[kThreads];
     __shared__ long long shc[kThreads];
@@ -264,18 +203,23 @@ __global__ __launch_bounds__(kThreads) void k_scan_top(dd* __restrict__ b1, dd* 
         on += vn;
     }
     if (threadIdx.x == 0) {
-        const double cnt = scal[2];
+        const double cnt = (double)(n - totn);
         double var = 0.0;
         if (cnt > 0) {
-            const double mean = (tot1.hi + tot1.lo) / cnt;
-            var = (tot2.hi + tot2.lo) / cnt - mean * mean;
+            // n var = sum x^2 - (sum x)^2 / n over the finite samples
+            const dd v = dd_sub(tot2, dd_div(dd_square(tot1), cnt));
+            var = (v.hi + v.lo) / cnt;
             if (var < 0) var = 0.0;
         }
+        scal[0] = 0.0;
         scal[1] = var;
+        scal[2] = cnt;
+        first[0] = ~0ull;
+        first[1] = ~0ull;
     }
 }
 
-// Pass 4: inclusive prefix arrays S1[t+1], S2[t+1], NF[t+1] (S[0] = 0).
+// Pass 3: inclusive prefix arrays S1[t+1], S2[t+1], NF[t+1] (S[0] = 0).
 __global__ __launch_bounds__(kThreads) void k_scan_local(const double* __restrict__ xc, int64_t n,
                                                          const dd* __restrict__ b1, const dd* __restrict__ b2,
                                                          const long long* __restrict__ bnf, dd* __restrict__ S1,
@@ -324,7 +268,7 @@ __global__ __launch_bounds__(kThreads) void k_scan_local(const double* __restric
     }
 }
 
-// Pass 5: per-window statistics, flags, recurrence terms and column records.
+// Pass 4: per-window statistics, flags, recurrence terms and column records.
 __global__ __launch_bounds__(kThreads) void k_window_stats(
     const double* __restrict__ xc, const dd* __restrict__ S1, const dd* __restrict__ S2,
     const int* __restrict__ NF, const double* __restrict__ scal, int64_t W, int m,
@@ -387,12 +331,6 @@ __global__ void k_fill_u64(unsigned long long* __restrict__ p, int64_t n, unsign
         p[t] = v;
 }
 
-__global__ void k_fill_f64(double* __restrict__ p, int64_t n, double v)
-{
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
-        p[t] = v;
-}
-
 __global__ void k_public_stats(const double* __restrict__ mu_c, const double* __restrict__ sig_in,
                                const uint8_t* __restrict__ fl_in, const double* __restrict__ scal, int64_t W,
                                double* __restrict__ mu, double* __restrict__ sig, uint8_t* __restrict__ fl)
@@ -421,7 +359,7 @@ int fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t
 
 size_t stats_scratch_bytes(int64_t n, int64_t W)
 {
-    const int64_t nb = nblocks_of(n);
+    const int64_t nb = nblocks_of(n + kSeriesPad);
     auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
     size_t b = 0;
     b += al(sizeof(double) * (size_t)(n + kSeriesPad));  // xc
@@ -431,8 +369,7 @@ size_t stats_scratch_bytes(int64_t n, int64_t W)
     b += al((size_t)W);                                  // flags
     b += al(sizeof(double) * 4);                         // scal
     b += al(sizeof(unsigned long long) * 2);             // first
-    // transient: partial sums, block sums, prefix arrays
-    b += al(sizeof(double) * kSumBlocks) + al(sizeof(long long) * kSumBlocks);
+    // transient: block sums, prefix arrays
     b += al(sizeof(dd) * (size_t)nb) * 2 + al(sizeof(long long) * (size_t)nb);
     b += al(sizeof(dd) * (size_t)(n + 1)) * 2 + al(sizeof(int) * (size_t)(n + 1));
     return b;
@@ -457,28 +394,19 @@ int stats_compute(const double* x, SeriesDev* s, const int64_t* seg_bounds_dev, 
                   hipStream_t stream)
 {
     const int64_t n = s->n;
-    const int64_t nb = nblocks_of(n);
-    double* psum = a.take<double>(kSumBlocks);
-    long long* pcnt = a.take<long long>(kSumBlocks);
-    dd* b1 = a.take<dd>((size_t)nb);
-    dd* b2 = a.take<dd>((size_t)nb);
-    long long* bnf = a.take<long long>((size_t)nb);
+    const int64_t nb = nblocks_of(n);              // blocks holding samples
+    const int64_t nbp = nblocks_of(n + kSeriesPad);  // ... and the zero tail
+    dd* b1 = a.take<dd>((size_t)nbp);
+    dd* b2 = a.take<dd>((size_t)nbp);
+    long long* bnf = a.take<long long>((size_t)nbp);
     dd* S1 = a.take<dd>((size_t)(n + 1));
     dd* S2 = a.take<dd>((size_t)(n + 1));
     int* NF = a.take<int>((size_t)(n + 1));
 
-    int parts = (int)((n + kThreads - 1) / kThreads);
-    if (parts > kSumBlocks) parts = kSumBlocks;
-    if (parts < 1) parts = 1;
-    hipLaunchKernelGGL(k_partial_sums, dim3(parts), dim3(kThreads), 0, stream, x, n, psum, pcnt);
-    hipLaunchKernelGGL(k_mean, dim3(1), dim3(kThreads), 0, stream, psum, pcnt, parts, s->scal);
-    hipLaunchKernelGGL(k_block_sums, dim3((unsigned)nb), dim3(kThreads), 0, stream, x, n, s->scal, s->xc, b1, b2,
-                       bnf);
-    hipLaunchKernelGGL(k_fill_f64, dim3(16), dim3(256), 0, stream, s->xc + n, (int64_t)kSeriesPad, 0.0);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kThreads), 0, stream, b1, b2, bnf, nb, s->scal);
+    hipLaunchKernelGGL(k_block_sums, dim3((unsigned)nbp), dim3(kThreads), 0, stream, x, n, s->xc, b1, b2, bnf);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kThreads), 0, stream, b1, b2, bnf, nb, n, s->scal, s->first);
     hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nb), dim3(kThreads), 0, stream, s->xc, n, b1, b2, bnf, S1, S2,
                        NF, x);
-    ABJ_TRY(fill_u64(s->first, 2, ~0ull, stream));
     if (s->W > 0) {
         const int64_t g = (s->W + kThreads - 1) / kThreads;
         hipLaunchKernelGGL(k_window_stats, dim3((unsigned)g), dim3(kThreads), 0, stream, s->xc, S1, S2, NF, s->scal,

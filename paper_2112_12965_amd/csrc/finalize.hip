@@ -68,7 +68,7 @@ __device__ inline unsigned long long outside_zone(unsigned long long first, cons
     return wave_find(bflags, WB, i + excl + 1, want_flat, lane);
 }
 
-__global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_finalize(
+__global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_finalize(
     const double* __restrict__ axc, const double* __restrict__ amu, const double* __restrict__ asig,
     const uint8_t* __restrict__ aflags, int64_t WA, const double* __restrict__ bxc, const double* __restrict__ bmu,
     const double* __restrict__ bsig, const unsigned long long* __restrict__ bfirst,
@@ -86,36 +86,25 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
     // jb + c of the row's winning group ----
     const int r = lane / kGroup, c = lane % kGroup;
     const int64_t i = row0 + r;
-    uint8_t fa = kFlagBad;
+    const int64_t ic = i < WA ? i : WA - 1;  // rows past the end read a valid row and are masked
+    // flags and key together (one memory round trip)
+    const uint8_t fa = i < WA ? aflags[ic] : (uint8_t)kFlagBad;
+    const unsigned long long key = keys ? keys[ic] : 0ull;
     int64_t jb = -1;
-    if (i < WA) {
-        fa = aflags[i];
-        if (keys && !(fa & (kFlagBad | kFlagFlat))) {
-            const unsigned long long key = keys[i];
-            if (key) jb = (int64_t)(0xFFFFFFFFu - (unsigned)(key & 0xFFFFFFFFull));
-        }
-    }
-    // statistics of the lane's candidate, loaded while the windows stream in
+    if (i < WA && key && !(fa & (kFlagBad | kFlagFlat))) jb = (int64_t)(0xFFFFFFFFu - (unsigned)(key & 0xFFFFFFFFull));
+    int64_t jrows[kRowsPerWave];
+#pragma unroll
+    for (int rr = 0; rr < kRowsPerWave; ++rr) jrows[rr] = __shfl(jb, rr * kGroup, kWave);
+    const bool any = jrows[0] >= 0 || jrows[1] >= 0 || jrows[2] >= 0 || jrows[3] >= 0;
+    // statistics of the lane's candidate and row (one more round trip, which
+    // the first pass's window loads below join)
     const int64_t j = jb + c;
     const bool cand = jb >= 0 && j < WB && (excl < 0 || j - i > excl || i - j > excl);
-    uint8_t fj = 1;
-    double mbj = 0.0, sbj = 1.0;
-    if (cand) {
-        fj = bflags[j];
-        mbj = bmu[j];
-        sbj = bsig[j];
-    }
-    const double mai = i < WA ? amu[i] : 0.0, sai = i < WA ? asig[i] : 1.0;
-    const double mb0 = jb >= 0 ? bmu[jb] : 0.0;
-    int64_t jrows[kRowsPerWave];
-    double mas[kRowsPerWave], mbs[kRowsPerWave];
-#pragma unroll
-    for (int rr = 0; rr < kRowsPerWave; ++rr) {
-        jrows[rr] = __shfl(jb, rr * kGroup, kWave);
-        mas[rr] = __shfl(mai, rr * kGroup, kWave);
-        mbs[rr] = __shfl(mb0, rr * kGroup, kWave);
-    }
-    const bool any = jrows[0] >= 0 || jrows[1] >= 0 || jrows[2] >= 0 || jrows[3] >= 0;
+    const int64_t jc = cand ? j : 0;
+    const uint8_t fj = cand ? bflags[jc] : (uint8_t)1;
+    const double mbj = bmu[jc], sbj = bsig[jc];
+    const double mai = amu[ic], sai = asig[ic];
+    const double mb0 = bmu[jb >= 0 ? jb : 0];
 
     // ---- choosing the column: FP32 dots of the row's window minus its mean
     // with the group's span minus the first candidate's mean (the candidates'
@@ -131,27 +120,43 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
     for (int kc = 0; kc < m; kc += kKC) {
         const int len = m - kc < kKC ? m - kc : kKC;
         if (any) {
+            // loads are unconditional (rows without a candidate read a valid
+            // address and store zeros) and all issued before the first use, so
+            // that they are in flight together
+            constexpr int kAL = kKC / kWave, kBL = (kBLen + kWave - 1) / kWave;
+            double la[kRowsPerWave][kAL], lb[kRowsPerWave][kBL];
+            double mas[kRowsPerWave], mbs[kRowsPerWave];
 #pragma unroll
             for (int rr = 0; rr < kRowsPerWave; ++rr) {
                 const int64_t jr = jrows[rr];
-                float va[kKC / kWave], vb[(kBLen + kWave - 1) / kWave];
+                const double* __restrict__ ar_ = axc + row0 + rr + kc;        // < n + 260: padded copy
+                const double* __restrict__ br_ = bxc + (jr >= 0 ? jr : 0) + kc;  // < n + 15: padded copy
 #pragma unroll
-                for (int x = 0; x < kKC / kWave; ++x) {
+                for (int x = 0; x < kAL; ++x) la[rr][x] = ar_[lane + x * kWave];
+#pragma unroll
+                for (int x = 0; x < kBL; ++x) {
                     const int t = lane + x * kWave;
-                    va[x] = (jr >= 0 && t < len) ? (float)(axc[row0 + rr + kc + t] - mas[rr]) : 0.f;
+                    lb[rr][x] = br_[t < kBLen ? t : kBLen - 1];
+                }
+            }
+#pragma unroll
+            for (int rr = 0; rr < kRowsPerWave; ++rr) {
+                mas[rr] = __shfl(mai, rr * kGroup, kWave);
+                mbs[rr] = __shfl(mb0, rr * kGroup, kWave);
+            }
+#pragma unroll
+            for (int rr = 0; rr < kRowsPerWave; ++rr) {
+                const bool live = jrows[rr] >= 0;
+#pragma unroll
+                for (int x = 0; x < kAL; ++x) {
+                    const int t = lane + x * kWave;
+                    sa[rr * kAPad + pad(t)] = (live && t < len) ? (float)(la[rr][x] - mas[rr]) : 0.f;
                 }
 #pragma unroll
-                for (int x = 0; x < (kBLen + kWave - 1) / kWave; ++x) {
+                for (int x = 0; x < kBL; ++x) {
                     const int t = lane + x * kWave;
-                    // < n + 15: inside the padded copy
-                    vb[x] = (jr >= 0 && t < len + kGroup - 1) ? (float)(bxc[jr + kc + t] - mbs[rr]) : 0.f;
-                }
-#pragma unroll
-                for (int x = 0; x < kKC / kWave; ++x) sa[rr * kAPad + pad(lane + x * kWave)] = va[x];
-#pragma unroll
-                for (int x = 0; x < (kBLen + kWave - 1) / kWave; ++x) {
-                    const int t = lane + x * kWave;
-                    if (t < kBLen) sb[rr * kBPad + pad(t)] = vb[x];
+                    if (t < kBLen)
+                        sb[rr * kBPad + pad(t)] = (live && t < len + kGroup - 1) ? (float)(lb[rr][x] - mbs[rr]) : 0.f;
                 }
             }
         }

@@ -276,7 +276,14 @@ int ab_join_dict(const abj_dict* d, const double* query, int64_t n_query, int32_
  * FP32 batch kernel (two launches in flight on two streams, so requests that
  * arrive while one batch runs join the next), and completes each request when
  * its batch finishes.  The BF16/FP16 tiers run admitted requests as separate
- * launches on the same two streams.
+ * launches on the same two streams.  A batch takes at most half of the slots
+ * and half of the budget (a lone request may take the whole budget), so the
+ * next batch can be formed and copied while one runs.  A batch costs one
+ * host-to-device copy
+ * (queries and descriptors) and one device-to-host copy (all results); each
+ * stream keeps a device work buffer and pinned staging buffers that grow to
+ * the largest batch it has run and are released by abj_server_destroy, so
+ * the device memory held stays within twice the budget plus descriptors.
  * ---------------------------------------------------------------------- */
 typedef struct abj_server abj_server;
 
@@ -315,6 +322,16 @@ int abj_server_create(const abj_dict* d, const abj_server_opts* opts, abj_server
  * rejected; others are unaffected); ABJ_ENOMEM if the request alone exceeds
  * the memory budget. */
 int abj_submit(abj_server* s, const double* query_host, int64_t n_query, int32_t m, uint64_t* req_id);
+/* Zero-copy form of abj_submit: the server thread reads query_host when the
+ * request is launched and writes the results straight into P_host and I_host
+ * (host memory, n_query-m+1 entries each) when its batch completes.  The
+ * caller keeps all three buffers alive, leaves the query unchanged and does
+ * not read P_host / I_host until abj_wait returns ABJ_OK (or the request is
+ * canceled); abj_result still has to be called to forget the request (its
+ * output pointers may then be NULL).  Same errors as abj_submit, plus
+ * ABJ_EINVAL for a NULL output. */
+int abj_submit_borrowed(abj_server* s, const double* query_host, int64_t n_query, int32_t m, float* P_host,
+                        int64_t* I_host, uint64_t* req_id);
 /* Blocks until the request is done (ABJ_OK), canceled (ABJ_ECANCELED) or the
  * timeout passes (ABJ_ETIMEOUT; timeout_ms < 0 waits forever).  ABJ_ENOTFOUND
  * for unknown ids. */

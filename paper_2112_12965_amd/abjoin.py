@@ -113,6 +113,7 @@ def lib():
         L.abj_server_create.argtypes = [_vp, ctypes.POINTER(abj_server_opts), ctypes.POINTER(_vp)]
         L.abj_submit.argtypes = [_vp, _vp, _i64, _i32, ctypes.POINTER(ctypes.c_uint64)]
         L.abj_wait.argtypes = [_vp, ctypes.c_uint64, _i32]
+        L.abj_submit_borrowed.argtypes = [_vp, _vp, _i64, _i32, _vp, _vp, ctypes.POINTER(ctypes.c_uint64)]
         L.abj_result.argtypes = [_vp, ctypes.c_uint64, _vp, _vp, ctypes.POINTER(abj_req_stats)]
         L.abj_cancel.argtypes = [_vp, ctypes.c_uint64]
         L.abj_server_drain.argtypes = [_vp, _i32]
@@ -120,8 +121,9 @@ def lib():
         L.abj_server_destroy.argtypes = [_vp]
         for f in ("abj_init", "abj_window_stats", "ab_join", "self_join", "dict_build", "topk_discords", "discords",
                   "abj_profile_enable", "abj_profile_read",
-                  "abj_dict_create", "abj_dict_free", "ab_join_dict", "abj_server_create", "abj_submit", "abj_wait",
-                  "abj_result", "abj_cancel", "abj_server_drain", "abj_server_stats_get", "abj_server_destroy"):
+                  "abj_dict_create", "abj_dict_free", "ab_join_dict", "abj_server_create", "abj_submit",
+                  "abj_submit_borrowed", "abj_wait", "abj_result", "abj_cancel", "abj_server_drain",
+                  "abj_server_stats_get", "abj_server_destroy"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -369,13 +371,28 @@ class Server:
                                        ctypes.byref(h)))
         self.handle = h
         self._dict = dictionary
-        self._lens = {}
+        self._reqs = {}  # id -> (rows, borrowed buffers or None)
 
-    def submit(self, query, m):
+    def submit(self, query, m, copy=False):
+        """Queue a join of `query` (host array) at window length m; returns the id.
+
+        By default the request borrows the query and result buffers (the
+        server reads and writes them on its own thread; this object keeps
+        them alive until result()); copy=True has the server copy the query
+        at submission instead.
+        """
         q = np.ascontiguousarray(np.asarray(query, dtype=np.float64))
+        W = len(q) - int(m) + 1
         rid = ctypes.c_uint64()
-        _check(lib().abj_submit(self.handle, q.ctypes.data, len(q), int(m), ctypes.byref(rid)))
-        self._lens[rid.value] = len(q) - int(m) + 1
+        if copy:
+            _check(lib().abj_submit(self.handle, q.ctypes.data, len(q), int(m), ctypes.byref(rid)))
+            self._reqs[rid.value] = (W, None)
+        else:
+            P = np.empty(max(W, 1), dtype=np.float32)
+            I = np.empty(max(W, 1), dtype=np.int64)
+            _check(lib().abj_submit_borrowed(self.handle, q.ctypes.data, len(q), int(m), P.ctypes.data,
+                                             I.ctypes.data, ctypes.byref(rid)))
+            self._reqs[rid.value] = (W, (q, P, I))
         return rid.value
 
     def wait(self, rid, timeout_ms=-1):
@@ -384,15 +401,21 @@ class Server:
 
     def result(self, rid):
         """(P, I, stats) of a finished request (numpy arrays, dict)."""
-        W = self._lens[rid]
-        P = np.empty(W, dtype=np.float32)
-        I = np.empty(W, dtype=np.int64)
+        W, keep = self._reqs[rid]
+        if keep is None:
+            P = np.empty(W, dtype=np.float32)
+            I = np.empty(W, dtype=np.int64)
+            ptrs = (P.ctypes.data, I.ctypes.data)
+        else:
+            P, I = keep[1][:W], keep[2][:W]
+            ptrs = (None, None)
         st = abj_req_stats()
-        rc = lib().abj_result(self.handle, ctypes.c_uint64(rid), P.ctypes.data, I.ctypes.data, ctypes.byref(st))
+        rc = lib().abj_result(self.handle, ctypes.c_uint64(rid), ptrs[0], ptrs[1], ctypes.byref(st))
         stats = {f: getattr(st, f) for f, _ in abj_req_stats._fields_}
+        if rc not in (ABJ_EBUSY, ABJ_ENOTFOUND):
+            del self._reqs[rid]  # the server has forgotten the request
         if rc != ABJ_OK:
             raise AbjError(rc, last_error())
-        del self._lens[rid]
         return P, I, stats
 
     def cancel(self, rid):

@@ -99,6 +99,16 @@ void stats_carve(Arena& a, int64_t n, int32_t m, SeriesDev* s);
 int stats_compute(const double* x, SeriesDev* s, const int64_t* seg_bounds_dev, int32_t n_seg, Arena& a,
                   hipStream_t stream);
 
+// Statistics of many query series in four launches (a serving batch): each
+// series' descriptor is written to job_host (stats_job_bytes() bytes) with its
+// arrays carved from `ar`; the block counters accumulate the launch grids.
+// clear: keys of the join to zero in the per-window pass (may be NULL).
+size_t stats_job_bytes();
+void stats_carve_job(Arena& a, const double* x_dev, int64_t n, int32_t m, SeriesDev* s, unsigned long long* clear,
+                     void* job_host, int64_t* blk_sum, int64_t* blk_loc, int64_t* blk_win);
+int stats_launch_many(const void* jobs_dev, int njobs, int64_t blk_sum, int64_t blk_loc, int64_t blk_win,
+                      hipStream_t stream);
+
 // Query rows per tile of the FP32 engine: slots whose rows start at a multiple
 // of this share the engine's tiling of the whole series.
 constexpr int64_t kFp32BandRows = 1024;
@@ -166,6 +176,13 @@ int join_fp32_batch(const Fp32Slot* slots_dev, int nslots, int64_t ntiles, int m
 // outside |j - i| <= excl.  pearson: report 1 - d^2 / (2m) instead of d.
 int finalize_launch(const SeriesDev& A, const SeriesDev& B, const unsigned long long* keys, float* P, int64_t* I,
                     hipStream_t stream, double* P64 = nullptr, int64_t excl = -1, bool pearson = false);
+
+// Row epilogues of many joins in one launch (a serving batch): one descriptor
+// per join (finalize_job_bytes() bytes, AB-join conventions), blocks counted in *blk.
+size_t finalize_job_bytes();
+void finalize_job(const SeriesDev& A, const SeriesDev& B, const unsigned long long* keys, float* P, int64_t* I,
+                  void* job_host, int64_t* blk);
+int finalize_launch_many(const void* jobs_dev, int njobs, int64_t blocks, hipStream_t stream);
 
 int fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t stream);
 

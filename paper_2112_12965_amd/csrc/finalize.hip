@@ -5,6 +5,7 @@
 // z-normalised windows, so there is no 1 - rho cancellation), and apply the
 // flat / non-finite conventions.
 #include <math.h>
+#include <string.h>
 
 #include "abj_internal.hpp"
 
@@ -68,17 +69,17 @@ __device__ inline unsigned long long outside_zone(unsigned long long first, cons
     return wave_find(bflags, WB, i + excl + 1, want_flat, lane);
 }
 
-__global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_finalize(
+__device__ __forceinline__ void finalize_body(
     const double* __restrict__ axc, const double* __restrict__ amu, const double* __restrict__ asig,
     const uint8_t* __restrict__ aflags, int64_t WA, const double* __restrict__ bxc, const double* __restrict__ bmu,
     const double* __restrict__ bsig, const unsigned long long* __restrict__ bfirst,
     const uint8_t* __restrict__ bflags, int64_t WB, int m, int64_t excl, int pearson,
     const unsigned long long* __restrict__ keys, float* __restrict__ P, int64_t* __restrict__ I,
-    double* __restrict__ P64)
+    double* __restrict__ P64, int64_t blk)
 {
     __shared__ float stage_all[kWavesPerBlock][kStage];
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-    const int64_t row0 = ((int64_t)blockIdx.x * kWavesPerBlock + wave) * kRowsPerWave;
+    const int64_t row0 = (blk * kWavesPerBlock + wave) * kRowsPerWave;
     float* __restrict__ sa = stage_all[wave];                              // per row: its centred window
     float* __restrict__ sb = stage_all[wave] + kRowsPerWave * kAPad;       // per row: its group's span
 
@@ -297,6 +298,51 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
     }
 }
 
+__global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_finalize(
+    const double* __restrict__ axc, const double* __restrict__ amu, const double* __restrict__ asig,
+    const uint8_t* __restrict__ aflags, int64_t WA, const double* __restrict__ bxc, const double* __restrict__ bmu,
+    const double* __restrict__ bsig, const unsigned long long* __restrict__ bfirst,
+    const uint8_t* __restrict__ bflags, int64_t WB, int m, int64_t excl, int pearson,
+    const unsigned long long* __restrict__ keys, float* __restrict__ P, int64_t* __restrict__ I,
+    double* __restrict__ P64)
+{
+    finalize_body(axc, amu, asig, aflags, WA, bxc, bmu, bsig, bfirst, bflags, WB, m, excl, pearson, keys, P, I, P64,
+                  blockIdx.x);
+}
+
+// Many joins per launch (a serving batch); workgroups never mix joins, so the
+// barriers inside see one window length.
+struct FinJobDev {
+    const double *axc, *amu, *asig;
+    const uint8_t* aflags;
+    int64_t WA;
+    const double *bxc, *bmu, *bsig;
+    const unsigned long long* bfirst;
+    const uint8_t* bflags;
+    int64_t WB;
+    int32_t m, pearson;
+    int64_t excl;
+    const unsigned long long* keys;
+    float* P;
+    int64_t* I;
+    double* P64;
+    int64_t blk0;
+};
+
+__global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_finalize_many(
+    const FinJobDev* __restrict__ jobs, int njobs)
+{
+    int lo = 0, hi = njobs;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (jobs[mid].blk0 <= (int64_t)blockIdx.x) lo = mid;
+        else hi = mid;
+    }
+    const FinJobDev& J = jobs[lo];
+    finalize_body(J.axc, J.amu, J.asig, J.aflags, J.WA, J.bxc, J.bmu, J.bsig, J.bfirst, J.bflags, J.WB, J.m, J.excl,
+                  J.pearson, J.keys, J.P, J.I, J.P64, (int64_t)blockIdx.x - J.blk0);
+}
+
 }  // namespace
 
 int finalize_launch(const SeriesDev& A, const SeriesDev& B, const unsigned long long* keys, float* P, int64_t* I,
@@ -307,6 +353,49 @@ int finalize_launch(const SeriesDev& A, const SeriesDev& B, const unsigned long 
     const int64_t g = (A.W + rows_per_block - 1) / rows_per_block;
     hipLaunchKernelGGL(k_finalize, dim3((unsigned)g), dim3(kWave * kWavesPerBlock), 0, stream, A.xc, A.mu, A.sig,
                        A.flags, A.W, B.xc, B.mu, B.sig, B.first, B.flags, B.W, (int)A.m, excl, pearson ? 1 : 0, keys, P, I, P64);
+    ABJ_HIP(hipGetLastError());
+    return ABJ_OK;
+}
+
+}  // namespace abj
+
+namespace abj {
+
+size_t finalize_job_bytes() { return sizeof(FinJobDev); }
+
+void finalize_job(const SeriesDev& A, const SeriesDev& B, const unsigned long long* keys, float* P, int64_t* I,
+                  void* job_host, int64_t* blk)
+{
+    FinJobDev J = {};
+    J.axc = A.xc;
+    J.amu = A.mu;
+    J.asig = A.sig;
+    J.aflags = A.flags;
+    J.WA = A.W;
+    J.bxc = B.xc;
+    J.bmu = B.mu;
+    J.bsig = B.sig;
+    J.bfirst = B.first;
+    J.bflags = B.flags;
+    J.WB = B.W;
+    J.m = A.m;
+    J.pearson = 0;
+    J.excl = -1;
+    J.keys = keys;
+    J.P = P;
+    J.I = I;
+    J.P64 = nullptr;
+    J.blk0 = *blk;
+    const int64_t rows_per_block = (int64_t)kWavesPerBlock * kRowsPerWave;
+    *blk += (A.W + rows_per_block - 1) / rows_per_block;
+    memcpy(job_host, &J, sizeof(J));
+}
+
+int finalize_launch_many(const void* jobs_dev, int njobs, int64_t blocks, hipStream_t stream)
+{
+    if (njobs <= 0 || blocks <= 0) return ABJ_OK;
+    hipLaunchKernelGGL(k_finalize_many, dim3((unsigned)blocks), dim3(kWave * kWavesPerBlock), 0, stream,
+                       static_cast<const FinJobDev*>(jobs_dev), njobs);
     ABJ_HIP(hipGetLastError());
     return ABJ_OK;
 }

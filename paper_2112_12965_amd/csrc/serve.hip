@@ -194,8 +194,15 @@ struct Req {
     abj_req_stats st{};
     std::vector<float> P;
     std::vector<int64_t> I;
-    // device side, valid while running
-    char* dmem = nullptr;
+    // zero-copy requests: the caller's buffers (then q, P and I stay empty)
+    const double* q_borrowed = nullptr;
+    float* P_out = nullptr;
+    int64_t* I_out = nullptr;
+    // device side, valid while running (inside the stream's work buffer)
+    const double* dq = nullptr;
+    char* work = nullptr;
+    size_t work_bytes = 0;
+    size_t off_P = 0, off_I = 0;  // offsets of the results in the staging buffer
     SeriesDev A;
     unsigned long long* keys = nullptr;
     float* dP = nullptr;
@@ -206,9 +213,22 @@ struct Batch {
     std::vector<Req*> reqs;
     int stream = 0;
     hipEvent_t ev = nullptr;
-    void* aux = nullptr;  // slot descriptors + tile counter
+    char* dout = nullptr;  // results region of the work buffer
+    size_t down = 0;
     double t_sim_done = 0;
     int status = ABJ_OK;
+};
+
+// Per-stream buffers kept for the server's lifetime and grown on demand: the
+// device work buffer and pinned staging for the batch copies.  A stream is
+// reused only after its previous batch has been collected.
+struct StreamBufs {
+    char* dev = nullptr;
+    size_t dev_bytes = 0;
+    char* hin = nullptr;
+    size_t hin_bytes = 0;
+    char* hout = nullptr;
+    size_t hout_bytes = 0;
 };
 
 }  // namespace
@@ -228,6 +248,7 @@ struct abj_server {
     bool stop = false;
     std::thread th;
     hipStream_t streams[2] = {nullptr, nullptr};
+    StreamBufs bufs[2];
     Clock::time_point t0;
     abj_server_stats stats{};
     double t_first_launch = -1, t_last_done = 0;
@@ -258,89 +279,157 @@ size_t req_bytes(const abj_server* s, int64_t n, int32_t m, MfmaPlan* plan)
     return b;
 }
 
-// Launch one batch on the GPU: per request, copy the query and compute its
-// statistics; then one persistent tile kernel over all FP32 requests (or one
-// launch per request in the 16-bit tiers); then each request's row epilogue.
+size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// cap: the largest batch the admission rule allows (budget plus descriptors).
+int grow_device(char** p, size_t* have, size_t want, size_t cap)
+{
+    if (*have >= want) return ABJ_OK;
+    // the previous batch on this stream has been collected, so the old buffer is idle
+    const size_t bytes = std::max(want, std::min(cap, *have + *have / 4 + ((size_t)1 << 20)));
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    *have = 0;
+    if (hipMalloc(reinterpret_cast<void**>(p), bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(ABJ_ENOMEM, "server work buffer of %zu bytes", bytes);
+    }
+    *have = bytes;
+    return ABJ_OK;
+}
+
+int grow_pinned(char** p, size_t* have, size_t want)
+{
+    if (*have >= want) return ABJ_OK;
+    if (*p) (void)hipHostFree(*p);
+    *p = nullptr;
+    const size_t bytes = std::max(want, *have + *have / 4 + ((size_t)1 << 20));
+    *have = 0;
+    if (hipHostMalloc(reinterpret_cast<void**>(p), bytes, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(ABJ_ENOMEM, "server staging buffer of %zu bytes", bytes);
+    }
+    *have = bytes;
+    return ABJ_OK;
+}
+
+// Launch one batch on the GPU.  The stream's work buffer is laid out as
+//   [descriptor tables | queries] [P of every request | I of every request] [work regions]
+// so that one copy brings the queries and descriptors in and one copy takes
+// the results out.  FP32 requests then take four statistics launches, one
+// persistent tile launch and one row-epilogue launch for the whole batch; the
+// 16-bit tiers run one join per request inside the same buffer.
 int launch_batch(abj_server* s, Batch& b)
 {
     hipStream_t st = s->streams[b.stream];
-    std::vector<Fp32Slot> slots;
-    int64_t tiles = 0, pairs = 0;
-    int max_m = 2;
+    StreamBufs& sb = s->bufs[b.stream];
+    const size_t k = b.reqs.size();
+    const bool fp32 = s->jo.tier == ABJ_TIER_FP32;
+    const size_t t_stats = al256(stats_job_bytes() * k), t_slots = al256(sizeof(Fp32Slot) * k),
+                 t_fin = al256(finalize_job_bytes() * k);
+    const size_t tables = fp32 ? t_stats + t_slots + t_fin + 256 : 0;
+    size_t qbytes = 0, pbytes = 0, ibytes = 0, work = 0;
     for (Req* r : b.reqs) {
-        ABJ_HIP(hipMallocAsync(reinterpret_cast<void**>(&r->dmem), r->mem, st));
-        Arena ar(r->dmem, r->mem);
-        double* dq = ar.take<double>((size_t)r->n);
-        r->dP = ar.take<float>((size_t)r->W);
-        r->dI = ar.take<int64_t>((size_t)r->W);
-        ABJ_HIP(hipMemcpyAsync(dq, r->q.data(), sizeof(double) * (size_t)r->n, hipMemcpyHostToDevice, st));
-        if (s->jo.tier != ABJ_TIER_FP32) {
-            ABJ_TRY(join_query(dq, r->n, r->m, r->dm->B, s->jo, r->plan, r->dP, r->dI, ar, st));
-            continue;
-        }
-        stats_carve(ar, r->n, r->m, &r->A);
-        r->keys = ar.take<unsigned long long>((size_t)r->W);
-        ar.take<Fp32Slot>(1);
-        ar.take<unsigned long long>(1);
-        ABJ_TRY(stats_compute(dq, &r->A, nullptr, 0, ar, st));
-        ABJ_TRY(fill_u64(r->keys, r->W, 0ull, st));
+        qbytes += al256(sizeof(double) * (size_t)r->n);
+        pbytes += al256(sizeof(float) * (size_t)r->W);
+        ibytes += al256(sizeof(int64_t) * (size_t)r->W);
+        work += query_scratch_bytes(r->n, r->m, r->dm->B.W, s->jo, r->plan);
+    }
+    const size_t up = tables + qbytes, down = pbytes + ibytes;
+    const size_t slots = (size_t)s->o.max_slots;
+    const size_t cap = (size_t)s->o.mem_budget + al256(stats_job_bytes() * slots) + al256(sizeof(Fp32Slot) * slots) +
+                       al256(finalize_job_bytes() * slots) + 256;
+    ABJ_TRY(grow_device(&sb.dev, &sb.dev_bytes, up + down + work, cap));
+    ABJ_TRY(grow_pinned(&sb.hin, &sb.hin_bytes, up));
+    ABJ_TRY(grow_pinned(&sb.hout, &sb.hout_bytes, down));
+    char* D = sb.dev;
+    char* H = sb.hin;
+    b.down = down;
+    b.dout = D + up;
+
+    size_t qo = tables, po = up, io = up + pbytes, wo = up + down;
+    int64_t blk_sum = 0, blk_loc = 0, blk_win = 0, blk_fin = 0, tiles = 0, pairs = 0;
+    int max_m = 2;
+    for (size_t a = 0; a < k; ++a) {
+        Req* r = b.reqs[a];
+        memcpy(H + qo, r->q_borrowed ? r->q_borrowed : r->q.data(), sizeof(double) * (size_t)r->n);
+        r->dq = reinterpret_cast<const double*>(D + qo);
+        qo += al256(sizeof(double) * (size_t)r->n);
+        r->dP = reinterpret_cast<float*>(D + po);
+        r->off_P = po - up;
+        po += al256(sizeof(float) * (size_t)r->W);
+        r->dI = reinterpret_cast<int64_t*>(D + io);
+        r->off_I = io - up;
+        io += al256(sizeof(int64_t) * (size_t)r->W);
+        r->work = D + wo;
+        r->work_bytes = query_scratch_bytes(r->n, r->m, r->dm->B.W, s->jo, r->plan);
+        wo += r->work_bytes;
+        if (!fp32) continue;
+        Arena ar(r->work, r->work_bytes);
+        const size_t key_bytes = sizeof(unsigned long long) * (size_t)r->W;
+        r->keys = ar.take<unsigned long long>(key_bytes / sizeof(unsigned long long));
+        stats_carve_job(ar, r->dq, r->n, r->m, &r->A, r->keys, H + a * stats_job_bytes(), &blk_sum, &blk_loc,
+                        &blk_win);
         Fp32Slot sl;
         fp32_slot(r->A, r->dm->B, r->keys, tiles, &sl);
         tiles += fp32_slot_tiles(sl);
         pairs += sl.pairs;
         max_m = std::max(max_m, (int)r->m);
-        slots.push_back(sl);
+        memcpy(H + t_stats + a * sizeof(Fp32Slot), &sl, sizeof(sl));
+        finalize_job(r->A, r->dm->B, r->keys, r->dP, r->dI, H + t_stats + t_slots + a * finalize_job_bytes(),
+                     &blk_fin);
     }
-    if (!slots.empty()) {
-        const size_t sb = sizeof(Fp32Slot) * slots.size();
-        const size_t aux = ((sb + 255) & ~size_t(255)) + 256;
-        ABJ_HIP(hipMallocAsync(&b.aux, aux, st));
-        Fp32Slot* dslots = static_cast<Fp32Slot*>(b.aux);
-        unsigned long long* counter =
-            reinterpret_cast<unsigned long long*>(static_cast<char*>(b.aux) + ((sb + 255) & ~size_t(255)));
-        ABJ_HIP(hipMemcpyAsync(dslots, slots.data(), sb, hipMemcpyHostToDevice, st));
-        ABJ_TRY(join_fp32_batch(dslots, (int)slots.size(), tiles, max_m, pairs, counter, st));
-        for (Req* r : b.reqs) ABJ_TRY(finalize_launch(r->A, r->dm->B, r->keys, r->dP, r->dI, st));
+    if (fp32) memset(H + tables - 256, 0, 256);  // tile counter
+    ABJ_HIP(hipMemcpyAsync(D, H, up, hipMemcpyHostToDevice, st));
+    if (fp32) {
+        ABJ_TRY(stats_launch_many(D, (int)k, blk_sum, blk_loc, blk_win, st));
+        ABJ_TRY(join_fp32_batch(reinterpret_cast<const Fp32Slot*>(D + t_stats), (int)k, tiles, max_m, pairs,
+                                reinterpret_cast<unsigned long long*>(D + tables - 256), st, false, true));
+        ABJ_TRY(finalize_launch_many(D + t_stats + t_slots, (int)k, blk_fin, st));
+    } else {
+        for (Req* r : b.reqs) {
+            Arena ar(r->work, r->work_bytes);
+            ABJ_TRY(join_query(r->dq, r->n, r->m, r->dm->B, s->jo, r->plan, r->dP, r->dI, ar, st));
+        }
     }
+    ABJ_HIP(hipMemcpyAsync(sb.hout, b.dout, down, hipMemcpyDeviceToHost, st));
     ABJ_HIP(hipEventCreateWithFlags(&b.ev, hipEventDisableTiming));
     ABJ_HIP(hipEventRecord(b.ev, st));
     return ABJ_OK;
 }
 
-// Copy a finished batch's results to the host and release its memory.
+// Move a finished batch's results out of the stream's staging buffer.
 int collect_batch(abj_server* s, Batch& b)
 {
     hipStream_t st = s->streams[b.stream];
     int rc = b.status;
-    for (Req* r : b.reqs) {
-        r->P.resize((size_t)r->W);
-        r->I.resize((size_t)r->W);
-        if (rc == ABJ_OK && r->dP) {
-            if (hipMemcpyAsync(r->P.data(), r->dP, sizeof(float) * (size_t)r->W, hipMemcpyDeviceToHost, st) !=
-                    hipSuccess ||
-                hipMemcpyAsync(r->I.data(), r->dI, sizeof(int64_t) * (size_t)r->W, hipMemcpyDeviceToHost, st) !=
-                    hipSuccess)
-                rc = set_error(ABJ_EHIP, "result copy failed");
-        }
-    }
     if (hipStreamSynchronize(st) != hipSuccess && rc == ABJ_OK) rc = set_error(ABJ_EHIP, "batch failed");
+    const char* H = s->bufs[b.stream].hout;
     for (Req* r : b.reqs) {
-        if (r->dmem) (void)hipFreeAsync(r->dmem, st);
-        r->dmem = nullptr;
+        if (rc != ABJ_OK) continue;
+        if (!r->P_out) {
+            r->P.resize((size_t)r->W);
+            r->I.resize((size_t)r->W);
+        }
+        memcpy(r->P_out ? r->P_out : r->P.data(), H + r->off_P, sizeof(float) * (size_t)r->W);
+        memcpy(r->I_out ? r->I_out : r->I.data(), H + r->off_I, sizeof(int64_t) * (size_t)r->W);
     }
-    if (b.aux) (void)hipFreeAsync(b.aux, st);
     if (b.ev) (void)hipEventDestroy(b.ev);
     return rc;
 }
 
 void sim_fill(abj_server* s, Req* r)
 {
-    r->P.resize((size_t)r->W);
-    r->I.resize((size_t)r->W);
+    if (!r->P_out) {
+        r->P.resize((size_t)r->W);
+        r->I.resize((size_t)r->W);
+    }
+    float* P = r->P_out ? r->P_out : r->P.data();
+    int64_t* I = r->I_out ? r->I_out : r->I.data();
     const int64_t wb = s->o.sim_dict_windows > 0 ? s->o.sim_dict_windows : 1;
     for (int64_t i = 0; i < r->W; ++i) {
-        r->P[(size_t)i] = (float)((i * 7 + (int64_t)r->id) % 100) * 0.1f;
-        r->I[(size_t)i] = i % wb;
+        P[i] = (float)((i * 7 + (int64_t)r->id) % 100) * 0.1f;
+        I[i] = i % wb;
     }
 }
 
@@ -367,7 +456,17 @@ void scheduler(abj_server* s)
                 s->cv_work.wait_for(lk, std::chrono::microseconds(50), [&] { return s->stop || admissible(); });
             }
             if (inflight.size() < 2) {
+                // half of the slots and of the budget per batch, so that the
+                // next batch can be formed while this one runs
+                const int slot_cap = std::max(1, s->o.max_slots / 2);
+                const int64_t mem_cap = s->o.mem_budget / 2;
+                int64_t batch_mem = 0;
                 while (admissible()) {
+                    const Req* nx = s->reqs[s->queue.front()].get();
+                    if (!b.reqs.empty() &&
+                        ((int)b.reqs.size() >= slot_cap || batch_mem + (int64_t)nx->mem > mem_cap))
+                        break;
+                    batch_mem += (int64_t)nx->mem;
                     Req* r = s->reqs[s->queue.front()].get();
                     s->queue.pop_front();
                     s->active += 1;
@@ -451,6 +550,12 @@ void scheduler(abj_server* s)
             inflight.pop_front();
         }
     }
+    for (StreamBufs& sb : s->bufs) {
+        if (sb.dev) (void)hipFree(sb.dev);
+        if (sb.hin) (void)hipHostFree(sb.hin);
+        if (sb.hout) (void)hipHostFree(sb.hout);
+        sb = StreamBufs();
+    }
 }
 
 }  // namespace
@@ -491,7 +596,8 @@ extern "C" int abj_server_create(const abj_dict* d, const abj_server_opts* opts,
     return ABJ_OK;
 }
 
-extern "C" int abj_submit(abj_server* s, const double* query_host, int64_t n_query, int32_t m, uint64_t* req_id)
+static int submit(abj_server* s, const double* query_host, int64_t n_query, int32_t m, float* P_out, int64_t* I_out,
+                  uint64_t* req_id)
 {
     if (!s || !query_host || !req_id) return set_error(ABJ_EINVAL, "NULL argument");
     int64_t WB = 0;
@@ -519,7 +625,13 @@ extern "C" int abj_submit(abj_server* s, const double* query_host, int64_t n_que
     if ((int64_t)r->mem > s->o.mem_budget) return reject(ABJ_ENOMEM, "request exceeds the memory budget");
     const int64_t nvalid = s->sim() ? WB : r->dm->B.nvalid;
     r->st.pairs = r->W * nvalid;
-    r->q.assign(query_host, query_host + n_query);
+    if (P_out) {
+        r->q_borrowed = query_host;
+        r->P_out = P_out;
+        r->I_out = I_out;
+    } else {
+        r->q.assign(query_host, query_host + n_query);
+    }
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->stop) return set_error(ABJ_EINVAL, "server is shutting down");
@@ -533,6 +645,18 @@ extern "C" int abj_submit(abj_server* s, const double* query_host, int64_t n_que
     }
     s->cv_work.notify_all();
     return ABJ_OK;
+}
+
+extern "C" int abj_submit(abj_server* s, const double* query_host, int64_t n_query, int32_t m, uint64_t* req_id)
+{
+    return submit(s, query_host, n_query, m, nullptr, nullptr, req_id);
+}
+
+extern "C" int abj_submit_borrowed(abj_server* s, const double* query_host, int64_t n_query, int32_t m,
+                                   float* P_host, int64_t* I_host, uint64_t* req_id)
+{
+    if (!P_host || !I_host) return set_error(ABJ_EINVAL, "P_host and I_host must not be NULL");
+    return submit(s, query_host, n_query, m, P_host, I_host, req_id);
 }
 
 extern "C" int abj_wait(abj_server* s, uint64_t id, int32_t timeout_ms)
@@ -563,8 +687,10 @@ extern "C" int abj_result(abj_server* s, uint64_t id, float* P_host, int64_t* I_
         return set_error(ABJ_EBUSY, "request %llu is not finished", (unsigned long long)id);
     if (st) *st = r->st;
     if (r->state == kDone && r->st.status == ABJ_OK) {
-        if (P_host) memcpy(P_host, r->P.data(), sizeof(float) * (size_t)r->W);
-        if (I_host) memcpy(I_host, r->I.data(), sizeof(int64_t) * (size_t)r->W);
+        const float* P = r->P_out ? r->P_out : r->P.data();
+        const int64_t* I = r->I_out ? r->I_out : r->I.data();
+        if (P_host && P_host != P) memcpy(P_host, P, sizeof(float) * (size_t)r->W);
+        if (I_host && I_host != I) memcpy(I_host, I, sizeof(int64_t) * (size_t)r->W);
     }
     const int rc = r->state == kCanceled ? ABJ_ECANCELED : r->st.status;
     s->reqs.erase(it);

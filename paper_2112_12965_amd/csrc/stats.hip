@@ -15,6 +15,7 @@
 // with which cov(i+1, j+1) = cov(i, j) + df_a(i) dg_b(j) + df_b(j) dg_a(i),
 // where cov(i, j) = sum_k (a[i+k] - mu_a(i)) (b[j+k] - mu_b(j)).
 #include <math.h>
+#include <string.h>
 
 #include "abj_internal.hpp"
 
@@ -128,13 +129,12 @@ __device__ inline long long block_excl_scan_i(long long v, long long* sh, long l
 // Pass 1: the working copy xc (non-finite -> 0, zero tail of kSeriesPad
 // samples) and per-block sums of xc, xc^2 (double-double) and the
 // non-finite count.
-__global__ __launch_bounds__(kThreads) void k_block_sums(const double* __restrict__ x, int64_t n,
-                                                         double* __restrict__ xc, dd* __restrict__ b1,
-                                                         dd* __restrict__ b2, long long* __restrict__ bnf)
+__device__ void block_sums_body(const double* __restrict__ x, int64_t n, double* __restrict__ xc,
+                                dd* __restrict__ b1, dd* __restrict__ b2, long long* __restrict__ bnf, int64_t blk)
 {
     __shared__ double shh[kThreads], shl[kThreads];
     __shared__ long long shc[kThreads];
-    const int64_t base = (int64_t)blockIdx.x * kBlockElems + (int64_t)threadIdx.x * kPerThread;
+    const int64_t base = blk * kBlockElems + (int64_t)threadIdx.x * kPerThread;
     dd s1 = {0.0, 0.0}, s2 = {0.0, 0.0};
     long long nf = 0;
 #pragma unroll
@@ -161,19 +161,17 @@ __global__ __launch_bounds__(kThreads) void k_block_sums(const double* __restric
     block_excl_scan_dd(s2, shh, shl, &t2);
     block_excl_scan_i(nf, shc, &tn);
     if (threadIdx.x == 0) {
-        b1[blockIdx.x] = t1;
-        b2[blockIdx.x] = t2;
-        bnf[blockIdx.x] = tn;
+        b1[blk] = t1;
+        b2[blk] = t2;
+        bnf[blk] = tn;
     }
 }
 
 // Pass 2: exclusive scan of the block sums (one workgroup); the series'
 // finite count -> scal[2], variance about its mean -> scal[1] (scal[0] = 0:
 // the working copy is not shifted); first[] reset for the per-window pass.
-__global__ __launch_bounds__(kThreads) void k_scan_top(dd* __restrict__ b1, dd* __restrict__ b2,
-                                                       long long* __restrict__ bnf, int64_t nb, int64_t n,
-                                                       double* __restrict__ scal,
-                                                       unsigned long long* __restrict__ first)
+__device__ void scan_top_body(dd* __restrict__ b1, dd* __restrict__ b2, long long* __restrict__ bnf, int64_t nb,
+                              int64_t n, double* __restrict__ scal, unsigned long long* __restrict__ first)
 {
     __shared__ double shh[kThreads], shl[kThreads];
     __shared__ long long shc[kThreads];
@@ -220,15 +218,13 @@ __global__ __launch_bounds__(kThreads) void k_scan_top(dd* __restrict__ b1, dd* 
 }
 
 // Pass 3: inclusive prefix arrays S1[t+1], S2[t+1], NF[t+1] (S[0] = 0).
-__global__ __launch_bounds__(kThreads) void k_scan_local(const double* __restrict__ xc, int64_t n,
-                                                         const dd* __restrict__ b1, const dd* __restrict__ b2,
-                                                         const long long* __restrict__ bnf, dd* __restrict__ S1,
-                                                         dd* __restrict__ S2, int* __restrict__ NF,
-                                                         const double* __restrict__ x)
+__device__ void scan_local_body(const double* __restrict__ xc, int64_t n, const dd* __restrict__ b1,
+                                const dd* __restrict__ b2, const long long* __restrict__ bnf, dd* __restrict__ S1,
+                                dd* __restrict__ S2, int* __restrict__ NF, const double* __restrict__ x, int64_t blk)
 {
     __shared__ double shh[kThreads], shl[kThreads];
     __shared__ long long shc[kThreads];
-    const int64_t base = (int64_t)blockIdx.x * kBlockElems + (int64_t)threadIdx.x * kPerThread;
+    const int64_t base = blk * kBlockElems + (int64_t)threadIdx.x * kPerThread;
     dd v1[kPerThread], v2[kPerThread];
     int vn[kPerThread];
     dd s1 = {0.0, 0.0}, s2 = {0.0, 0.0};
@@ -249,9 +245,9 @@ __global__ __launch_bounds__(kThreads) void k_scan_local(const double* __restric
         v2[e] = s2;
         vn[e] = (int)nf;
     }
-    const dd o1 = dd_add(block_excl_scan_dd(s1, shh, shl, nullptr), b1[blockIdx.x]);
-    const dd o2 = dd_add(block_excl_scan_dd(s2, shh, shl, nullptr), b2[blockIdx.x]);
-    const long long on = block_excl_scan_i(nf, shc, nullptr) + bnf[blockIdx.x];
+    const dd o1 = dd_add(block_excl_scan_dd(s1, shh, shl, nullptr), b1[blk]);
+    const dd o2 = dd_add(block_excl_scan_dd(s2, shh, shl, nullptr), b2[blk]);
+    const long long on = block_excl_scan_i(nf, shc, nullptr) + bnf[blk];
 #pragma unroll
     for (int e = 0; e < kPerThread; ++e) {
         const int64_t t = base + e;
@@ -261,7 +257,7 @@ __global__ __launch_bounds__(kThreads) void k_scan_local(const double* __restric
             NF[t + 1] = (int)(on + vn[e]);
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (blk == 0 && threadIdx.x == 0) {
         S1[0] = {0.0, 0.0};
         S2[0] = {0.0, 0.0};
         NF[0] = 0;
@@ -269,15 +265,16 @@ __global__ __launch_bounds__(kThreads) void k_scan_local(const double* __restric
 }
 
 // Pass 4: per-window statistics, flags, recurrence terms and column records.
-__global__ __launch_bounds__(kThreads) void k_window_stats(
-    const double* __restrict__ xc, const dd* __restrict__ S1, const dd* __restrict__ S2,
-    const int* __restrict__ NF, const double* __restrict__ scal, int64_t W, int m,
-    const int64_t* __restrict__ bounds, int n_seg, double* __restrict__ mu, double* __restrict__ sig,
-    float2* __restrict__ dfdg, float4* __restrict__ col, uint8_t* __restrict__ flags,
-    unsigned long long* __restrict__ first)
+__device__ void window_stats_body(const double* __restrict__ xc, const dd* __restrict__ S1,
+                                  const dd* __restrict__ S2, const int* __restrict__ NF,
+                                  const double* __restrict__ scal, int64_t W, int m,
+                                  const int64_t* __restrict__ bounds, int n_seg, double* __restrict__ mu,
+                                  double* __restrict__ sig, float2* __restrict__ dfdg, float4* __restrict__ col,
+                                  uint8_t* __restrict__ flags, unsigned long long* __restrict__ first,
+                                  unsigned long long* __restrict__ clear, int64_t i)
 {
-    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (i >= W) return;
+    if (clear) clear[i] = 0ull;  // the join's key for this row
     const double inv_m = 1.0 / (double)m;
     const double gvar = scal[1];
     // window sums of xc and xc^2, then m var = sum xc^2 - (sum xc)^2 / m, all in
@@ -323,6 +320,104 @@ __global__ __launch_bounds__(kThreads) void k_window_stats(
         atomicMin(&first[1], (unsigned long long)i);
         if (f & kFlagFlat) atomicMin(&first[0], (unsigned long long)i);
     }
+}
+
+// One series per launch.
+__global__ __launch_bounds__(kThreads) void k_block_sums(const double* __restrict__ x, int64_t n,
+                                                         double* __restrict__ xc, dd* __restrict__ b1,
+                                                         dd* __restrict__ b2, long long* __restrict__ bnf)
+{
+    block_sums_body(x, n, xc, b1, b2, bnf, blockIdx.x);
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_top(dd* __restrict__ b1, dd* __restrict__ b2,
+                                                       long long* __restrict__ bnf, int64_t nb, int64_t n,
+                                                       double* __restrict__ scal,
+                                                       unsigned long long* __restrict__ first)
+{
+    scan_top_body(b1, b2, bnf, nb, n, scal, first);
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_local(const double* __restrict__ xc, int64_t n,
+                                                         const dd* __restrict__ b1, const dd* __restrict__ b2,
+                                                         const long long* __restrict__ bnf, dd* __restrict__ S1,
+                                                         dd* __restrict__ S2, int* __restrict__ NF,
+                                                         const double* __restrict__ x)
+{
+    scan_local_body(xc, n, b1, b2, bnf, S1, S2, NF, x, blockIdx.x);
+}
+
+__global__ __launch_bounds__(kThreads) void k_window_stats(
+    const double* __restrict__ xc, const dd* __restrict__ S1, const dd* __restrict__ S2,
+    const int* __restrict__ NF, const double* __restrict__ scal, int64_t W, int m,
+    const int64_t* __restrict__ bounds, int n_seg, double* __restrict__ mu, double* __restrict__ sig,
+    float2* __restrict__ dfdg, float4* __restrict__ col, uint8_t* __restrict__ flags,
+    unsigned long long* __restrict__ first)
+{
+    window_stats_body(xc, S1, S2, NF, scal, W, m, bounds, n_seg, mu, sig, dfdg, col, flags, first, nullptr,
+                      (int64_t)blockIdx.x * kThreads + threadIdx.x);
+}
+
+// Many series per launch (a serving batch): each workgroup finds its series
+// in the job table by its block number.
+struct StatsJobDev {
+    const double* x;
+    double* xc;
+    int64_t n, W;
+    int32_t m, pad0;
+    dd *b1, *b2;
+    long long* bnf;
+    dd *S1, *S2;
+    int* NF;
+    double *mu, *sig;
+    float2* dfdg;
+    float4* col;
+    uint8_t* flags;
+    double* scal;
+    unsigned long long* first;
+    unsigned long long* clear;  // keys of the join to clear (W entries)
+    int64_t blk_sum, blk_loc, blk_win;  // first block of this series in each launch's grid
+};
+
+// Last job whose first block (field F) is <= b.
+template <int64_t StatsJobDev::*F>
+__device__ inline int find_job(const StatsJobDev* __restrict__ jobs, int njobs, int64_t b)
+{
+    int lo = 0, hi = njobs;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (jobs[mid].*F <= b) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kThreads) void k_block_sums_many(const StatsJobDev* __restrict__ jobs, int njobs)
+{
+    const int jx = find_job<&StatsJobDev::blk_sum>(jobs, njobs, blockIdx.x);
+    const StatsJobDev& J = jobs[jx];
+    block_sums_body(J.x, J.n, J.xc, J.b1, J.b2, J.bnf, (int64_t)blockIdx.x - J.blk_sum);
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_top_many(const StatsJobDev* __restrict__ jobs)
+{
+    const StatsJobDev& J = jobs[blockIdx.x];
+    scan_top_body(J.b1, J.b2, J.bnf, (J.n + kBlockElems - 1) / kBlockElems, J.n, J.scal, J.first);
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_local_many(const StatsJobDev* __restrict__ jobs, int njobs)
+{
+    const int jx = find_job<&StatsJobDev::blk_loc>(jobs, njobs, blockIdx.x);
+    const StatsJobDev& J = jobs[jx];
+    scan_local_body(J.xc, J.n, J.b1, J.b2, J.bnf, J.S1, J.S2, J.NF, J.x, (int64_t)blockIdx.x - J.blk_loc);
+}
+
+__global__ __launch_bounds__(kThreads) void k_window_stats_many(const StatsJobDev* __restrict__ jobs, int njobs)
+{
+    const int jx = find_job<&StatsJobDev::blk_win>(jobs, njobs, blockIdx.x);
+    const StatsJobDev& J = jobs[jx];
+    window_stats_body(J.xc, J.S1, J.S2, J.NF, J.scal, J.W, J.m, nullptr, 0, J.mu, J.sig, J.dfdg, J.col, J.flags,
+                      nullptr, J.clear, ((int64_t)blockIdx.x - J.blk_win) * kThreads + threadIdx.x);
 }
 
 __global__ void k_fill_u64(unsigned long long* __restrict__ p, int64_t n, unsigned long long v)
@@ -413,6 +508,56 @@ int stats_compute(const double* x, SeriesDev* s, const int64_t* seg_bounds_dev, 
                            s->W, (int)s->m, seg_bounds_dev, (int)n_seg, s->mu, s->sig, s->dfdg, s->col, s->flags,
                            seg_bounds_dev ? s->first : nullptr);
     }
+    ABJ_HIP(hipGetLastError());
+    return ABJ_OK;
+}
+
+size_t stats_job_bytes() { return sizeof(StatsJobDev); }
+
+void stats_carve_job(Arena& a, const double* x_dev, int64_t n, int32_t m, SeriesDev* s, unsigned long long* clear,
+                     void* job_host, int64_t* blk_sum, int64_t* blk_loc, int64_t* blk_win)
+{
+    stats_carve(a, n, m, s);
+    StatsJobDev J = {};
+    const int64_t nb = nblocks_of(n), nbp = nblocks_of(n + kSeriesPad);
+    J.x = x_dev;
+    J.xc = s->xc;
+    J.n = n;
+    J.W = s->W;
+    J.m = m;
+    J.b1 = a.take<dd>((size_t)nbp);
+    J.b2 = a.take<dd>((size_t)nbp);
+    J.bnf = a.take<long long>((size_t)nbp);
+    J.S1 = a.take<dd>((size_t)(n + 1));
+    J.S2 = a.take<dd>((size_t)(n + 1));
+    J.NF = a.take<int>((size_t)(n + 1));
+    J.mu = s->mu;
+    J.sig = s->sig;
+    J.dfdg = s->dfdg;
+    J.col = s->col;
+    J.flags = s->flags;
+    J.scal = s->scal;
+    J.first = s->first;
+    J.clear = clear;
+    J.blk_sum = *blk_sum;
+    J.blk_loc = *blk_loc;
+    J.blk_win = *blk_win;
+    *blk_sum += nbp;
+    *blk_loc += nb;
+    *blk_win += (s->W + kThreads - 1) / kThreads;
+    memcpy(job_host, &J, sizeof(J));
+}
+
+int stats_launch_many(const void* jobs_dev, int njobs, int64_t blk_sum, int64_t blk_loc, int64_t blk_win,
+                      hipStream_t stream)
+{
+    if (njobs <= 0) return ABJ_OK;
+    const StatsJobDev* J = static_cast<const StatsJobDev*>(jobs_dev);
+    hipLaunchKernelGGL(k_block_sums_many, dim3((unsigned)blk_sum), dim3(kThreads), 0, stream, J, njobs);
+    hipLaunchKernelGGL(k_scan_top_many, dim3((unsigned)njobs), dim3(kThreads), 0, stream, J);
+    hipLaunchKernelGGL(k_scan_local_many, dim3((unsigned)blk_loc), dim3(kThreads), 0, stream, J, njobs);
+    if (blk_win > 0)
+        hipLaunchKernelGGL(k_window_stats_many, dim3((unsigned)blk_win), dim3(kThreads), 0, stream, J, njobs);
     ABJ_HIP(hipGetLastError());
     return ABJ_OK;
 }

@@ -1,10 +1,10 @@
 """GPU tests of the resident dictionary and the continuous-batching server.
 
 * ab_join_dict equals ab_join on the same inputs (bitwise);
-* every served result equals the same request joined alone through the
-  resident dictionary (bitwise: a request's tiles and arithmetic do not depend
-  on what else shares its launch), under mixed query lengths and window
-  lengths, with queueing forced by slot and memory limits;
+* every served result (query copied or borrowed) equals the same request
+  joined alone through the resident dictionary (bitwise: a request's tiles and
+  arithmetic do not depend on what else shares its launch), under mixed query
+  lengths and window lengths, with queueing forced by slot and memory limits;
 * served results meet the FP32 parity bar against the FP64 oracle.
 """
 import numpy as np
@@ -53,14 +53,15 @@ def alone(d, q, m, tier):
     return P.cpu().numpy(), I.cpu().numpy()
 
 
-@pytest.mark.parametrize("tier,slots,budget", [("fp32", 64, 8 << 30), ("fp32", 3, 8 << 30),
-                                               ("fp32", 64, 24 << 20), ("bf16", 8, 8 << 30)])
-def test_served_equals_alone(served_dict, tier, slots, budget):
+@pytest.mark.parametrize("tier,slots,budget,copy", [("fp32", 64, 8 << 30, False), ("fp32", 64, 8 << 30, True),
+                                                    ("fp32", 3, 8 << 30, False), ("fp32", 64, 24 << 20, False),
+                                                    ("bf16", 8, 8 << 30, False), ("bf16", 8, 8 << 30, True)])
+def test_served_equals_alone(served_dict, tier, slots, budget, copy):
     w, d = served_dict
     reqs = requests(24, seed=7)
-    print(f"[case] server tier={tier} slots={slots} budget={budget}", flush=True)
+    print(f"[case] server tier={tier} slots={slots} budget={budget} copy={copy}", flush=True)
     srv = abjoin.Server(d, tier=tier, max_slots=slots, mem_budget=budget)
-    ids = [srv.submit(q, m) for q, m in reqs]
+    ids = [srv.submit(q, m, copy=copy) for q, m in reqs]
     res = []
     for i in ids:
         assert srv.wait(i, 60000) == abjoin.ABJ_OK, abjoin.last_error()

@@ -128,3 +128,34 @@ def test_drain_and_destroy_with_pending_requests():
     assert srv.stats()["completed"] == 20
     more = [srv.submit(np.zeros(60000), 64) for _ in range(10)]
     srv.close()  # cancels what is still queued; must not hang
+
+
+def test_copied_and_borrowed_submissions():
+    srv = make()
+    rng = np.random.default_rng(3)
+    qs = [rng.standard_normal(int(n)) for n in rng.integers(1024, 4096, 8)]
+    ids = [srv.submit(q, 64, copy=(k % 2 == 0)) for k, q in enumerate(qs)]
+    for i in ids:
+        assert srv.wait(i, 20000) == abjoin.ABJ_OK
+    for rid, q in zip(ids, qs):
+        P, I, st = srv.result(rid)
+        W = len(q) - 63
+        assert P.shape == (W,) and I.shape == (W,) and st["status"] == 0
+        np.testing.assert_allclose(P, ((np.arange(W) * 7 + rid) % 100) * 0.1, rtol=1e-6)
+    assert not srv._reqs  # borrowed buffers are released with the result
+    with pytest.raises(abjoin.AbjError) as e:
+        srv.submit(np.zeros(10), 64)
+    assert e.value.code == abjoin.ABJ_EINVAL
+    srv.close()
+
+
+def test_batch_takes_half_the_slots():
+    srv = make(max_slots=8, sim_pairs_per_s=2e11)
+    ids = [srv.submit(np.zeros(4096), 64) for _ in range(24)]
+    assert srv.drain(60000) == abjoin.ABJ_OK
+    per_batch = {}
+    for i in ids:
+        b = srv.result(i)[2]["batch"]
+        per_batch[b] = per_batch.get(b, 0) + 1
+    assert max(per_batch.values()) <= 4 and len(per_batch) >= 6
+    srv.close()

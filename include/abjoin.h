@@ -273,17 +273,18 @@ int ab_join_dict(const abj_dict* d, const double* query, int64_t n_query, int32_
  * Serving: continuous batching of joins against a resident dictionary.
  * A scheduler thread admits queued requests while a slot and memory are
  * free, launches every admitted request's tiles together in one persistent
- * FP32 batch kernel (two launches in flight on two streams, so requests that
- * arrive while one batch runs join the next), and completes each request when
- * its batch finishes.  The BF16/FP16 tiers run admitted requests as separate
- * launches on the same two streams.  A batch takes at most half of the slots
- * and half of the budget (a lone request may take the whole budget), so the
- * next batch can be formed and copied while one runs.  A batch costs one
- * host-to-device copy
- * (queries and descriptors) and one device-to-host copy (all results); each
- * stream keeps a device work buffer and pinned staging buffers that grow to
- * the largest batch it has run and are released by abj_server_destroy, so
- * the device memory held stays within twice the budget plus descriptors.
+ * FP32 batch kernel (two launches in flight, in order on the server's
+ * stream, so requests that arrive while one batch runs join the next), and
+ * completes each request when its batch finishes: a completion thread copies
+ * the results out while the next batches run.  The BF16/FP16 tiers run
+ * admitted requests as separate launches on the same stream.  A batch takes
+ * at most half of the slots and half of the budget (a lone request may take
+ * the whole budget), so the next batch can be formed and queued while one
+ * runs.  A batch costs one host-to-device copy (queries and descriptors) and
+ * one device-to-host copy (all results); each of the two batch buffer sets
+ * keeps a device work buffer and pinned staging that grow to the largest
+ * batch it has run and are released by abj_server_destroy, so the device
+ * memory held stays within twice the budget plus descriptors.
  * ---------------------------------------------------------------------- */
 typedef struct abj_server abj_server;
 
@@ -302,10 +303,11 @@ typedef struct {
     double t_arrive; /* seconds since server creation: submit */
     double t_admit;  /* admitted (slot + memory granted) */
     double t_start;  /* its batch was launched */
-    double t_done;   /* results on the host */
+    double t_done;   /* results delivered to the host buffers */
     int64_t pairs;   /* valid pairs of the request */
     int32_t status;  /* ABJ_OK, ABJ_ECANCELED, or an error code */
     int32_t batch;   /* launch the request ran in */
+    double t_device_done;  /* its batch finished on the device (slot and memory released) */
 } abj_req_stats;
 
 typedef struct {

@@ -59,7 +59,7 @@ class abj_server_opts(ctypes.Structure):
 class abj_req_stats(ctypes.Structure):
     _fields_ = [("t_arrive", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_start", ctypes.c_double),
                 ("t_done", ctypes.c_double), ("pairs", ctypes.c_int64), ("status", ctypes.c_int32),
-                ("batch", ctypes.c_int32)]
+                ("batch", ctypes.c_int32), ("t_device_done", ctypes.c_double)]
 
 
 class abj_server_stats(ctypes.Structure):

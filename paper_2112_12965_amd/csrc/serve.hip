@@ -9,11 +9,13 @@
 //   * continuous batching: every request admitted since the last launch goes
 //     into the next launch; FP32 requests share ONE persistent tile kernel
 //     (each request contributes its row-band x column-chunk tiles), so their
-//     work overlaps on the device; two launches are kept in flight on two
-//     streams, so requests arriving while one runs are launched at once;
-//   * completion: when a launch's event fires, its requests' results are
-//     copied to the host, their memory and slots are released and waiters
-//     are woken.
+//     work overlaps on the device; two launches are kept in flight, in order
+//     on one stream with a buffer set each, so the next batch is queued on
+//     the device while one runs and a batch's epilogue never competes with
+//     the next batch's tiles;
+//   * completion: when a launch's event fires its slots and memory are
+//     released, and a completion thread copies the results to the requests'
+//     buffers and wakes the waiters.
 // The host-simulation backend runs the same scheduler without any GPU call
 // (execution time = pairs / configured rate) so that admission, ordering,
 // cancellation and statistics can be tested on a machine without a GPU.
@@ -211,24 +213,24 @@ struct Req {
 
 struct Batch {
     std::vector<Req*> reqs;
-    int stream = 0;
+    int set = 0;  // buffer set
     hipEvent_t ev = nullptr;
     char* dout = nullptr;  // results region of the work buffer
     size_t down = 0;
+    char* hout = nullptr;  // pinned copy of the results region (from the server's pool)
+    size_t hout_bytes = 0;
     double t_sim_done = 0;
     int status = ABJ_OK;
 };
 
-// Per-stream buffers kept for the server's lifetime and grown on demand: the
-// device work buffer and pinned staging for the batch copies.  A stream is
-// reused only after its previous batch has been collected.
-struct StreamBufs {
+// Buffers of one batch in flight, kept for the server's lifetime and grown on
+// demand: the device work buffer and pinned staging for the upload.  A set is
+// reused only after its previous batch has finished on the device.
+struct BufferSet {
     char* dev = nullptr;
     size_t dev_bytes = 0;
     char* hin = nullptr;
     size_t hin_bytes = 0;
-    char* hout = nullptr;
-    size_t hout_bytes = 0;
 };
 
 }  // namespace
@@ -247,8 +249,18 @@ struct abj_server {
     int64_t mem_used = 0;
     bool stop = false;
     std::thread th;
-    hipStream_t streams[2] = {nullptr, nullptr};
-    StreamBufs bufs[2];
+    hipStream_t stream = nullptr;
+    BufferSet bufs[2];  // one set per batch in flight
+    // batches finished on the device, whose results the completion thread
+    // moves to the requests' buffers; pinned result buffers cycle through a pool
+    std::mutex cmu;
+    std::condition_variable cv_comp;
+    std::deque<Batch> finished;
+    bool comp_stop = false;
+    std::vector<std::pair<char*, size_t>> out_pool;
+    std::vector<char*> retired;  // outgrown pinned buffers, freed at destroy
+    int64_t completing = 0;  // requests handed to the completion thread (under mu)
+    std::thread comp;
     Clock::time_point t0;
     abj_server_stats stats{};
     double t_first_launch = -1, t_last_done = 0;
@@ -281,32 +293,40 @@ size_t req_bytes(const abj_server* s, int64_t n, int32_t m, MfmaPlan* plan)
 
 size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// cap: the largest batch the admission rule allows (budget plus descriptors).
-int grow_device(char** p, size_t* have, size_t want, size_t cap)
+// Buffers grow geometrically, without any device-wide synchronisation: the
+// device buffer is replaced in stream order (the stream's previous batch is
+// the last user of the old one), and an outgrown pinned buffer is retired
+// until the server is destroyed (freeing pinned memory can wait for the whole
+// device).  cap: the largest batch the admission rule allows.
+int grow_device(char** p, size_t* have, size_t want, size_t cap, hipStream_t st)
 {
     if (*have >= want) return ABJ_OK;
-    // the previous batch on this stream has been collected, so the old buffer is idle
-    const size_t bytes = std::max(want, std::min(cap, *have + *have / 4 + ((size_t)1 << 20)));
-    if (*p) (void)hipFree(*p);
+    const size_t bytes = std::max(want, std::min(cap, 2 * *have));
+    if (*p) (void)hipFreeAsync(*p, st);
     *p = nullptr;
     *have = 0;
-    if (hipMalloc(reinterpret_cast<void**>(p), bytes) != hipSuccess) {
+    if (hipMallocAsync(reinterpret_cast<void**>(p), bytes, st) != hipSuccess) {
         (void)hipGetLastError();
+        *p = nullptr;
         return set_error(ABJ_ENOMEM, "server work buffer of %zu bytes", bytes);
     }
     *have = bytes;
     return ABJ_OK;
 }
 
-int grow_pinned(char** p, size_t* have, size_t want)
+int grow_pinned(abj_server* s, char** p, size_t* have, size_t want)
 {
     if (*have >= want) return ABJ_OK;
-    if (*p) (void)hipHostFree(*p);
+    const size_t bytes = std::max(want, std::max(2 * *have, (size_t)1 << 20));
+    if (*p) {
+        std::lock_guard<std::mutex> lk(s->cmu);
+        s->retired.push_back(*p);
+    }
     *p = nullptr;
-    const size_t bytes = std::max(want, *have + *have / 4 + ((size_t)1 << 20));
     *have = 0;
     if (hipHostMalloc(reinterpret_cast<void**>(p), bytes, hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
+        *p = nullptr;
         return set_error(ABJ_ENOMEM, "server staging buffer of %zu bytes", bytes);
     }
     *have = bytes;
@@ -321,8 +341,8 @@ int grow_pinned(char** p, size_t* have, size_t want)
 // 16-bit tiers run one join per request inside the same buffer.
 int launch_batch(abj_server* s, Batch& b)
 {
-    hipStream_t st = s->streams[b.stream];
-    StreamBufs& sb = s->bufs[b.stream];
+    hipStream_t st = s->stream;
+    BufferSet& sb = s->bufs[b.set];
     const size_t k = b.reqs.size();
     const bool fp32 = s->jo.tier == ABJ_TIER_FP32;
     const size_t t_stats = al256(stats_job_bytes() * k), t_slots = al256(sizeof(Fp32Slot) * k),
@@ -339,9 +359,17 @@ int launch_batch(abj_server* s, Batch& b)
     const size_t slots = (size_t)s->o.max_slots;
     const size_t cap = (size_t)s->o.mem_budget + al256(stats_job_bytes() * slots) + al256(sizeof(Fp32Slot) * slots) +
                        al256(finalize_job_bytes() * slots) + 256;
-    ABJ_TRY(grow_device(&sb.dev, &sb.dev_bytes, up + down + work, cap));
-    ABJ_TRY(grow_pinned(&sb.hin, &sb.hin_bytes, up));
-    ABJ_TRY(grow_pinned(&sb.hout, &sb.hout_bytes, down));
+    ABJ_TRY(grow_device(&sb.dev, &sb.dev_bytes, up + down + work, cap, st));
+    ABJ_TRY(grow_pinned(s, &sb.hin, &sb.hin_bytes, up));
+    {
+        std::lock_guard<std::mutex> lk(s->cmu);
+        if (!s->out_pool.empty()) {
+            b.hout = s->out_pool.back().first;
+            b.hout_bytes = s->out_pool.back().second;
+            s->out_pool.pop_back();
+        }
+    }
+    ABJ_TRY(grow_pinned(s, &b.hout, &b.hout_bytes, down));
     char* D = sb.dev;
     char* H = sb.hin;
     b.down = down;
@@ -392,29 +420,29 @@ int launch_batch(abj_server* s, Batch& b)
             ABJ_TRY(join_query(r->dq, r->n, r->m, r->dm->B, s->jo, r->plan, r->dP, r->dI, ar, st));
         }
     }
-    ABJ_HIP(hipMemcpyAsync(sb.hout, b.dout, down, hipMemcpyDeviceToHost, st));
+    ABJ_HIP(hipMemcpyAsync(b.hout, b.dout, down, hipMemcpyDeviceToHost, st));
     ABJ_HIP(hipEventCreateWithFlags(&b.ev, hipEventDisableTiming));
     ABJ_HIP(hipEventRecord(b.ev, st));
     return ABJ_OK;
 }
 
-// Move a finished batch's results out of the stream's staging buffer.
-int collect_batch(abj_server* s, Batch& b)
+// Move a finished batch's results out of its pinned buffer (completion
+// thread; the batch's event has fired).
+int collect_batch(Batch& b)
 {
-    hipStream_t st = s->streams[b.stream];
     int rc = b.status;
-    if (hipStreamSynchronize(st) != hipSuccess && rc == ABJ_OK) rc = set_error(ABJ_EHIP, "batch failed");
-    const char* H = s->bufs[b.stream].hout;
+    if (rc == ABJ_OK && b.ev && hipEventSynchronize(b.ev) != hipSuccess) rc = set_error(ABJ_EHIP, "batch failed");
     for (Req* r : b.reqs) {
         if (rc != ABJ_OK) continue;
         if (!r->P_out) {
             r->P.resize((size_t)r->W);
             r->I.resize((size_t)r->W);
         }
-        memcpy(r->P_out ? r->P_out : r->P.data(), H + r->off_P, sizeof(float) * (size_t)r->W);
-        memcpy(r->I_out ? r->I_out : r->I.data(), H + r->off_I, sizeof(int64_t) * (size_t)r->W);
+        memcpy(r->P_out ? r->P_out : r->P.data(), b.hout + r->off_P, sizeof(float) * (size_t)r->W);
+        memcpy(r->I_out ? r->I_out : r->I.data(), b.hout + r->off_I, sizeof(int64_t) * (size_t)r->W);
     }
     if (b.ev) (void)hipEventDestroy(b.ev);
+    b.ev = nullptr;
     return rc;
 }
 
@@ -437,7 +465,7 @@ void scheduler(abj_server* s)
 {
     if (!s->sim()) (void)hipSetDevice(s->device);
     std::deque<Batch> inflight;
-    int next_stream = 0;
+    int next_set = 0;
     int64_t batch_no = 0;
     for (;;) {
         Batch b;
@@ -478,8 +506,8 @@ void scheduler(abj_server* s)
             }
         }
         if (!b.reqs.empty()) {
-            b.stream = next_stream;
-            next_stream ^= 1;
+            b.set = next_set;
+            next_set ^= 1;
             const double t = s->now();
             int64_t pairs = 0;
             for (Req* r : b.reqs) {
@@ -519,42 +547,78 @@ void scheduler(abj_server* s)
                 }
             }
             if (!done) break;
-            int rc = ob.status;
-            if (s->sim()) {
-                for (Req* r : ob.reqs) sim_fill(s, r);
-            } else {
-                rc = collect_batch(s, ob);
-            }
+            // the device is done with this batch: free its slots and memory
+            // now, and let the completion thread deliver the results
+            if (!s->sim() && ob.status != ABJ_OK) (void)hipStreamSynchronize(s->stream);
             {
                 std::lock_guard<std::mutex> lk(s->mu);
                 const double t = s->now();
                 for (Req* r : ob.reqs) {
-                    r->state = kDone;
-                    r->st.status = rc;
-                    r->st.t_done = t;
-                    r->q.clear();
-                    r->q.shrink_to_fit();
+                    r->st.t_device_done = t;
                     s->active -= 1;
                     s->mem_used -= (int64_t)r->mem;
-                    if (rc == ABJ_OK) {
-                        s->stats.completed += 1;
-                        s->stats.pairs += r->st.pairs;
-                        s->lat.push_back(r->st.t_done - r->st.t_arrive);
-                    }
                 }
-                s->stats.batches += 1;
-                s->t_last_done = t;
+                s->completing += (int64_t)ob.reqs.size();
             }
-            s->cv_done.notify_all();
-            s->cv_work.notify_all();
+            {
+                std::lock_guard<std::mutex> lk(s->cmu);
+                s->finished.push_back(std::move(ob));
+            }
+            s->cv_comp.notify_one();
             inflight.pop_front();
         }
     }
-    for (StreamBufs& sb : s->bufs) {
-        if (sb.dev) (void)hipFree(sb.dev);
+    for (int k = 0; k < 2; ++k) {
+        BufferSet& sb = s->bufs[k];
+        if (sb.dev) (void)hipFreeAsync(sb.dev, s->stream);
+        if (s->stream) (void)hipStreamSynchronize(s->stream);
         if (sb.hin) (void)hipHostFree(sb.hin);
-        if (sb.hout) (void)hipHostFree(sb.hout);
-        sb = StreamBufs();
+        sb = BufferSet();
+    }
+}
+
+void completer(abj_server* s)
+{
+    if (!s->sim()) (void)hipSetDevice(s->device);
+    for (;;) {
+        Batch b;
+        {
+            std::unique_lock<std::mutex> lk(s->cmu);
+            s->cv_comp.wait(lk, [&] { return s->comp_stop || !s->finished.empty(); });
+            if (s->finished.empty()) break;
+            b = std::move(s->finished.front());
+            s->finished.pop_front();
+        }
+        int rc = b.status;
+        if (s->sim()) {
+            for (Req* r : b.reqs) sim_fill(s, r);
+        } else {
+            rc = collect_batch(b);
+        }
+        if (b.hout) {
+            std::lock_guard<std::mutex> lk(s->cmu);
+            s->out_pool.emplace_back(b.hout, b.hout_bytes);
+        }
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            const double t = s->now();
+            for (Req* r : b.reqs) {
+                r->state = kDone;
+                r->st.status = rc;
+                r->st.t_done = t;
+                r->q.clear();
+                r->q.shrink_to_fit();
+                if (rc == ABJ_OK) {
+                    s->stats.completed += 1;
+                    s->stats.pairs += r->st.pairs;
+                    s->lat.push_back(r->st.t_done - r->st.t_arrive);
+                }
+            }
+            s->completing -= (int64_t)b.reqs.size();
+            s->stats.batches += 1;
+            s->t_last_done = t;
+        }
+        s->cv_done.notify_all();
     }
 }
 
@@ -582,15 +646,14 @@ extern "C" int abj_server_create(const abj_dict* d, const abj_server_opts* opts,
     if (o.backend == 0) {
         int rc = ensure_device();
         if (rc == ABJ_OK && hipGetDevice(&s->device) != hipSuccess) rc = set_error(ABJ_EHIP, "hipGetDevice failed");
-        for (int k = 0; k < 2 && rc == ABJ_OK; ++k)
-            if (hipStreamCreate(&s->streams[k]) != hipSuccess) rc = set_error(ABJ_EHIP, "stream creation failed");
+        if (rc == ABJ_OK && hipStreamCreate(&s->stream) != hipSuccess)
+            rc = set_error(ABJ_EHIP, "stream creation failed");
         if (rc != ABJ_OK) {
-            for (auto& st : s->streams)
-                if (st) (void)hipStreamDestroy(st);
             delete s;
             return rc;
         }
     }
+    s->comp = std::thread(completer, s);
     s->th = std::thread(scheduler, s);
     *out = s;
     return ABJ_OK;
@@ -722,7 +785,7 @@ extern "C" int abj_server_drain(abj_server* s, int32_t timeout_ms)
 {
     if (!s) return set_error(ABJ_EINVAL, "server is NULL");
     std::unique_lock<std::mutex> lk(s->mu);
-    auto idle = [&] { return s->queue.empty() && s->active == 0; };
+    auto idle = [&] { return s->queue.empty() && s->active == 0 && s->completing == 0; };
     if (timeout_ms < 0) {
         s->cv_done.wait(lk, idle);
     } else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), idle)) {
@@ -768,8 +831,15 @@ extern "C" int abj_server_destroy(abj_server* s)
     s->cv_work.notify_all();
     s->cv_done.notify_all();
     if (s->th.joinable()) s->th.join();
-    for (auto& st : s->streams)
-        if (st) (void)hipStreamDestroy(st);
+    {
+        std::lock_guard<std::mutex> lk(s->cmu);
+        s->comp_stop = true;
+    }
+    s->cv_comp.notify_all();
+    if (s->comp.joinable()) s->comp.join();
+    for (auto& e : s->out_pool) (void)hipHostFree(e.first);
+    for (char* p : s->retired) (void)hipHostFree(p);
+    if (s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
     return ABJ_OK;
 }

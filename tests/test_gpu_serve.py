@@ -75,7 +75,7 @@ def test_served_equals_alone(served_dict, tier, slots, budget, copy):
     for (q, m), (P, I, rs) in zip(reqs, res):
         Pa, Ia = alone(d, q, m, tier)
         assert np.array_equal(P, Pa) and np.array_equal(I, Ia)
-        assert rs["t_arrive"] <= rs["t_admit"] <= rs["t_start"] <= rs["t_done"]
+        assert rs["t_arrive"] <= rs["t_admit"] <= rs["t_start"] <= rs["t_device_done"] <= rs["t_done"]
 
 
 def test_served_results_match_oracle(served_dict, orc):

@@ -37,7 +37,7 @@ def test_results_and_timestamps():
         assert P.shape == (W,) and I.shape == (W,)
         i = np.arange(W)
         np.testing.assert_allclose(P, ((i * 7 + rid) % 100) * 0.1, rtol=1e-6)
-        assert st["t_arrive"] <= st["t_admit"] <= st["t_start"] <= st["t_done"]
+        assert st["t_arrive"] <= st["t_admit"] <= st["t_start"] <= st["t_device_done"] <= st["t_done"]
         assert st["pairs"] == W * 60000 and st["status"] == 0
     s = srv.stats()
     assert s["submitted"] == 12 and s["completed"] == 12 and s["pairs"] == sum(r[2]["pairs"] for r in res)
@@ -46,7 +46,9 @@ def test_results_and_timestamps():
 
 
 def _max_overlap(stats):
-    ev = sorted([(s["t_admit"], 1) for s in stats] + [(s["t_done"], -1) for s in stats], key=lambda e: (e[0], e[1]))
+    # slots and memory are held from admission until the device has finished
+    ev = sorted([(s["t_admit"], 1) for s in stats] + [(s["t_device_done"], -1) for s in stats],
+                key=lambda e: (e[0], e[1]))
     cur = best = 0
     for _, d in ev:
         cur += d
@@ -73,7 +75,7 @@ def test_single_slot_is_sequential_and_fifo():
     _, res = run_all(srv, reqs)
     st = [r[2] for r in res]
     for a, b in zip(st, st[1:]):
-        assert b["t_admit"] >= a["t_done"] - 1e-9  # admitted only after the previous one finished
+        assert b["t_admit"] >= a["t_device_done"] - 1e-9  # admitted only after the previous one finished
         assert b["t_admit"] >= a["t_admit"]        # in submission order
     srv.close()
 
@@ -86,7 +88,7 @@ def test_continuous_batching_launches_while_busy():
     assert srv.wait(a, 20000) == 0 and srv.wait(b, 20000) == 0
     sa, sb = srv.result(a)[2], srv.result(b)[2]
     assert sb["batch"] == sa["batch"] + 1
-    assert sb["t_start"] < sa["t_done"]  # launched while the first launch was still running
+    assert sb["t_start"] < sa["t_device_done"]  # launched while the first launch was still running
     srv.close()
 
 

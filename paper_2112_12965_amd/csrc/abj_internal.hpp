@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "abjoin.h"
 
 namespace abj {
@@ -103,9 +105,12 @@ int stats_compute(const double* x, SeriesDev* s, const int64_t* seg_bounds_dev, 
 // series' descriptor is written to job_host (stats_job_bytes() bytes) with its
 // arrays carved from `ar`; the block counters accumulate the launch grids.
 // clear: keys of the join to zero in the per-window pass (may be NULL).
+// bounds_dev / n_seg: segment bounds of a reference series (device), which
+// mask segment-crossing windows and find the first flat / valid window.
 size_t stats_job_bytes();
 void stats_carve_job(Arena& a, const double* x_dev, int64_t n, int32_t m, SeriesDev* s, unsigned long long* clear,
-                     void* job_host, int64_t* blk_sum, int64_t* blk_loc, int64_t* blk_win);
+                     void* job_host, int64_t* blk_sum, int64_t* blk_loc, int64_t* blk_win,
+                     const int64_t* bounds_dev = nullptr, int32_t n_seg = 0);
 int stats_launch_many(const void* jobs_dev, int njobs, int64_t blk_sum, int64_t blk_loc, int64_t blk_win,
                       hipStream_t stream);
 
@@ -158,6 +163,8 @@ void fp32_slot(const SeriesDev& A, const SeriesDev& B, unsigned long long* keys,
 // Carves the list from `ar` and copies it to the device for B; with dbounds
 // the same copy also brings the segment bounds (*dbounds points at them).
 size_t fp32_chunk_bytes(int32_t n_seg, int64_t n);
+// The chunk list itself (pairs [start, end) of reference windows), host side.
+std::vector<int32_t> fp32_chunk_list(const int64_t* bounds, int32_t n_seg, int64_t n, int32_t m);
 int fp32_chunks_upload(const int64_t* bounds, int32_t n_seg, int64_t n, int32_t m, Arena& ar, SeriesDev* B,
                        hipStream_t stream, int64_t** dbounds = nullptr);
 int64_t fp32_slot_tiles(const Fp32Slot& sl);
@@ -212,7 +219,8 @@ int check_opts(const abj_opts* opts, abj_opts* out);
 constexpr int32_t kMaxM = 4096;
 constexpr int64_t kMaxN = (1LL << 31) - 1;
 
-// Device bytes that join_query needs for one query of n samples.
+// Device bytes that join_query needs for one query of n samples (statistics,
+// keys, the upload region and, in the 16-bit tiers, the MFMA operands).
 size_t query_scratch_bytes(int64_t n, int32_t m, int64_t WB, const abj_opts& o, const MfmaPlan& plan);
 // Query-side join against reference statistics B: query statistics, pair loop
 // of the selected tier, row epilogue.  All scratch comes from `ar`.

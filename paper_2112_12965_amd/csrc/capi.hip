@@ -149,38 +149,93 @@ int check_opts(const abj_opts* opts, abj_opts* out)
     return ABJ_OK;
 }
 
+namespace {
+size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+}  // namespace
+
 size_t query_scratch_bytes(int64_t n, int32_t m, int64_t WB, const abj_opts& o, const MfmaPlan& plan)
 {
     (void)WB;
     const int64_t W = n - m + 1;
     size_t b = stats_scratch_bytes(n, W);
-    b += (sizeof(unsigned long long) * (size_t)W + 255) & ~size_t(255);
-    b += 256;  // tile counter
-    b += 256;  // slot descriptor
+    b += al256(sizeof(unsigned long long) * (size_t)W);  // keys
+    // upload region: statistics job, slot descriptor, tile counter
+    b += al256(stats_job_bytes()) + al256(sizeof(Fp32Slot)) + 256;
     if (o.tier != ABJ_TIER_FP32) b += mfma_scratch_bytes(plan);
     return b;
+}
+
+size_t pair_scratch_bytes(int64_t n_query, int64_t n_ref, int32_t n_seg, int32_t m, const abj_opts& o,
+                          const MfmaPlan& plan)
+{
+    const int64_t WB = n_ref >= m ? n_ref - m + 1 : 0;
+    return stats_scratch_bytes(n_ref, WB) + fp32_chunk_bytes(n_seg, n_ref) + al256(stats_job_bytes()) +
+           query_scratch_bytes(n_query, m, WB, o, plan);
+}
+
+// The whole path of one join: the statistics of the query (and of the
+// reference, when `ref` is given with its host segment bounds; else `Bres`
+// holds them) in four launches, the pair scores and the row epilogue.  The
+// descriptors, the reference's segment bounds and chunk list and the zeroed
+// tile counter are built on the host and uploaded in one copy; the
+// per-window statistics pass clears the FP32 keys.
+int join_run(const double* query, int64_t n, int32_t m, const double* ref, int64_t n_ref, const int64_t* ref_bounds,
+             int32_t n_seg, const SeriesDev* Bres, const abj_opts& o, const MfmaPlan& plan, float* P, int64_t* I,
+             Arena& ar, hipStream_t stream)
+{
+    const bool fp32 = o.tier == ABJ_TIER_FP32;
+    const bool pearson = (o.flags & ABJ_FLAG_PEARSON) != 0;
+    const int njobs = ref ? 2 : 1;
+    const size_t jb = stats_job_bytes();
+    std::vector<int32_t> chunks;
+    if (ref) chunks = fp32_chunk_list(ref_bounds, n_seg, n_ref, m);
+    const size_t nb = ref ? (size_t)(n_seg + 1) : 0;
+    const size_t o_chunks = sizeof(int64_t) * nb;
+    const size_t o_jobs = al256(o_chunks + sizeof(int32_t) * chunks.size());
+    const size_t o_slot = o_jobs + al256(jb * (size_t)njobs);
+    const size_t o_counter = o_slot + al256(sizeof(Fp32Slot));
+    const size_t up = o_counter + 256;
+    char* U = ar.take<char>(up);
+    std::vector<char> h(up, 0);
+    int64_t bs = 0, bl = 0, bw = 0;
+    SeriesDev B;
+    if (ref) {
+        if (nb) memcpy(h.data(), ref_bounds, o_chunks);
+        if (!chunks.empty()) memcpy(h.data() + o_chunks, chunks.data(), sizeof(int32_t) * chunks.size());
+        stats_carve_job(ar, ref, n_ref, m, &B, nullptr, h.data() + o_jobs, &bs, &bl, &bw,
+                        reinterpret_cast<const int64_t*>(U), n_seg);
+        B.chunks = reinterpret_cast<const int32_t*>(U + o_chunks);
+        B.nchunks = (int64_t)chunks.size() / 2;
+        for (int32_t sgi = 0; sgi < n_seg; ++sgi) {
+            const int64_t len = ref_bounds[sgi + 1] - ref_bounds[sgi];
+            if (len >= m) B.nvalid += len - m + 1;
+        }
+    } else {
+        B = *Bres;
+    }
+    SeriesDev A;
+    const int64_t WA = n - m + 1;
+    unsigned long long* keys = ar.take<unsigned long long>((size_t)WA);
+    stats_carve_job(ar, query, n, m, &A, fp32 ? keys : nullptr, h.data() + o_jobs + (size_t)(njobs - 1) * jb, &bs,
+                    &bl, &bw);
+    Fp32Slot sl = {};
+    if (fp32) {
+        fp32_slot(A, B, keys, 0, &sl);
+        memcpy(h.data() + o_slot, &sl, sizeof(sl));
+    }
+    ABJ_HIP(hipMemcpyAsync(U, h.data(), up, hipMemcpyHostToDevice, stream));
+    ABJ_TRY(stats_launch_many(U + o_jobs, njobs, bs, bl, bw, stream));
+    if (!fp32)
+        return join_mfma_run(A, B, plan, !(o.flags & ABJ_FLAG_NO_REFINE), pearson, P, I, ar, stream);
+    ABJ_TRY(join_fp32_batch(reinterpret_cast<const Fp32Slot*>(U + o_slot), 1, fp32_slot_tiles(sl), m, sl.pairs,
+                            reinterpret_cast<unsigned long long*>(U + o_counter), stream, false, true));
+    return finalize_launch(A, B, keys, P, I, stream, nullptr, -1, pearson);
 }
 
 int join_query(const double* query, int64_t n, int32_t m, const SeriesDev& B, const abj_opts& o,
                const MfmaPlan& plan, float* P, int64_t* I, Arena& ar, hipStream_t stream)
 {
-    SeriesDev A;
-    stats_carve(ar, n, m, &A);
-    // keys and the tile counter are adjacent pieces: one fill clears both
-    const size_t key_words = ((sizeof(unsigned long long) * (size_t)A.W + 255) & ~size_t(255)) / 8;
-    unsigned long long* keys = ar.take<unsigned long long>((size_t)A.W);
-    unsigned long long* counter = ar.take<unsigned long long>(1);
-    Fp32Slot* dslot = ar.take<Fp32Slot>(1);
-    ABJ_TRY(stats_compute(query, &A, nullptr, 0, ar, stream));
-    if (o.tier != ABJ_TIER_FP32)
-        return join_mfma_run(A, B, plan, !(o.flags & ABJ_FLAG_NO_REFINE), (o.flags & ABJ_FLAG_PEARSON) != 0, P, I,
-                             ar, stream);
-    ABJ_TRY(fill_u64(keys, (int64_t)key_words + 1, 0ull, stream));
-    Fp32Slot sl;
-    fp32_slot(A, B, keys, 0, &sl);
-    ABJ_HIP(hipMemcpyAsync(dslot, &sl, sizeof(sl), hipMemcpyHostToDevice, stream));
-    ABJ_TRY(join_fp32_batch(dslot, 1, fp32_slot_tiles(sl), m, sl.pairs, counter, stream, false, true));
-    return finalize_launch(A, B, keys, P, I, stream, nullptr, -1, (o.flags & ABJ_FLAG_PEARSON) != 0);
+    return join_run(query, n, m, nullptr, 0, nullptr, 0, &B, o, plan, P, I, ar, stream);
 }
 
 int stats_export(const SeriesDev& s, double* mu, double* sig, uint8_t* flags, hipStream_t stream);
@@ -281,18 +336,7 @@ extern "C" int ab_join(const double* query, int64_t n_query, const double* dict,
 
     hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
     Arena ar(stream);
-    ar.reserve(stats_scratch_bytes(n_dict, WB));
-    ar.reserve(fp32_chunk_bytes(n_seg, n_dict));  // chunk list and segment bounds
-    ar.reserve(query_scratch_bytes(n_query, m, WB, o, plan));
+    ar.reserve(pair_scratch_bytes(n_query, n_dict, n_seg, m, o, plan));
     ABJ_TRY(ar.commit());
-    SeriesDev B;
-    stats_carve(ar, n_dict, m, &B);
-    int64_t* dbounds = nullptr;
-    ABJ_TRY(fp32_chunks_upload(seg_bounds, n_seg, n_dict, m, ar, &B, stream, &dbounds));
-    for (int32_t sgi = 0; sgi < n_seg; ++sgi) {
-        const int64_t len = seg_bounds[sgi + 1] - seg_bounds[sgi];
-        if (len >= m) B.nvalid += len - m + 1;
-    }
-    ABJ_TRY(stats_compute(dict, &B, dbounds, n_seg, ar, stream));
-    return join_query(query, n_query, m, B, o, plan, P_AB, I_AB, ar, stream);
+    return join_run(query, n_query, m, dict, n_dict, seg_bounds, n_seg, nullptr, o, plan, P_AB, I_AB, ar, stream);
 }

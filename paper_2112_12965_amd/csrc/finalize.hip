@@ -338,7 +338,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
         if (jobs[mid].blk0 <= (int64_t)blockIdx.x) lo = mid;
         else hi = mid;
     }
-    const FinJobDev& J = jobs[lo];
+    const FinJobDev& J = jobs[__builtin_amdgcn_readfirstlane(lo)];
     finalize_body(J.axc, J.amu, J.asig, J.aflags, J.WA, J.bxc, J.bmu, J.bsig, J.bfirst, J.bflags, J.WB, J.m, J.excl,
                   J.pearson, J.keys, J.P, J.I, J.P64, (int64_t)blockIdx.x - J.blk0);
 }

@@ -394,8 +394,7 @@ size_t fp32_chunk_bytes(int32_t n_seg, int64_t n)
     return (bounds + sizeof(int32_t) * 2 * (size_t)most + 255) & ~size_t(255);
 }
 
-int fp32_chunks_upload(const int64_t* bounds, int32_t n_seg, int64_t n, int32_t m, Arena& ar, SeriesDev* B,
-                       hipStream_t stream, int64_t** dbounds)
+std::vector<int32_t> fp32_chunk_list(const int64_t* bounds, int32_t n_seg, int64_t n, int32_t m)
 {
     std::vector<int32_t> c;
     auto split = [&](int64_t a, int64_t cnt) {
@@ -416,6 +415,13 @@ int fp32_chunks_upload(const int64_t* bounds, int32_t n_seg, int64_t n, int32_t 
             if (len >= m) split(bounds[s], len - m + 1);
         }
     }
+    return c;
+}
+
+int fp32_chunks_upload(const int64_t* bounds, int32_t n_seg, int64_t n, int32_t m, Arena& ar, SeriesDev* B,
+                       hipStream_t stream, int64_t** dbounds)
+{
+    const std::vector<int32_t> c = fp32_chunk_list(bounds, n_seg, n, m);
     // one copy: the segment bounds (when asked for), then the chunk list
     const size_t nb = (dbounds && n_seg > 0) ? (size_t)(n_seg + 1) : 0;
     std::vector<int64_t> buf(nb + (c.size() + 1) / 2, 0);

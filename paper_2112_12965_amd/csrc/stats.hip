@@ -316,9 +316,14 @@ __device__ void window_stats_body(const double* __restrict__ xc, const dd* __res
     const bool usable = f == 0;
     // bias -inf: the window never wins a row (the FP32 engine adds it to every score)
     col[i] = make_float4(df, dg, usable ? (float)(1.0 / sd) : 0.f, usable ? 0.f : -INFINITY);
-    if (first && !(f & (kFlagBad | kFlagInvalid))) {
-        atomicMin(&first[1], (unsigned long long)i);
-        if (f & kFlagFlat) atomicMin(&first[0], (unsigned long long)i);
+    if (first) {
+        // one atomic per wave: windows ascend with the lane, so the lowest
+        // lane of each ballot holds the wave's first valid / flat window
+        const bool valid = !(f & (kFlagBad | kFlagInvalid));
+        const unsigned long long bv = __ballot(valid), bf = __ballot(valid && (f & kFlagFlat));
+        const int lane = (int)__lane_id();
+        if (bv && lane == __ffsll((long long)bv) - 1) atomicMin(&first[1], (unsigned long long)i);
+        if (bf && lane == __ffsll((long long)bf) - 1) atomicMin(&first[0], (unsigned long long)i);
     }
 }
 
@@ -376,10 +381,14 @@ struct StatsJobDev {
     double* scal;
     unsigned long long* first;
     unsigned long long* clear;  // keys of the join to clear (W entries)
+    const int64_t* bounds;      // segment bounds of a reference series, or NULL
+    int64_t n_seg;
     int64_t blk_sum, blk_loc, blk_win;  // first block of this series in each launch's grid
 };
 
 // Last job whose first block (field F) is <= b.
+// (The result is made wave-uniform explicitly, so that the job's fields are
+// scalar loads.)
 template <int64_t StatsJobDev::*F>
 __device__ inline int find_job(const StatsJobDev* __restrict__ jobs, int njobs, int64_t b)
 {
@@ -389,7 +398,7 @@ __device__ inline int find_job(const StatsJobDev* __restrict__ jobs, int njobs, 
         if (jobs[mid].*F <= b) lo = mid;
         else hi = mid;
     }
-    return lo;
+    return __builtin_amdgcn_readfirstlane(lo);
 }
 
 __global__ __launch_bounds__(kThreads) void k_block_sums_many(const StatsJobDev* __restrict__ jobs, int njobs)
@@ -416,8 +425,9 @@ __global__ __launch_bounds__(kThreads) void k_window_stats_many(const StatsJobDe
 {
     const int jx = find_job<&StatsJobDev::blk_win>(jobs, njobs, blockIdx.x);
     const StatsJobDev& J = jobs[jx];
-    window_stats_body(J.xc, J.S1, J.S2, J.NF, J.scal, J.W, J.m, nullptr, 0, J.mu, J.sig, J.dfdg, J.col, J.flags,
-                      nullptr, J.clear, ((int64_t)blockIdx.x - J.blk_win) * kThreads + threadIdx.x);
+    window_stats_body(J.xc, J.S1, J.S2, J.NF, J.scal, J.W, J.m, J.bounds, (int)J.n_seg, J.mu, J.sig, J.dfdg, J.col,
+                      J.flags, J.bounds ? J.first : nullptr, J.clear,
+                      ((int64_t)blockIdx.x - J.blk_win) * kThreads + threadIdx.x);
 }
 
 __global__ void k_fill_u64(unsigned long long* __restrict__ p, int64_t n, unsigned long long v)
@@ -515,7 +525,8 @@ int stats_compute(const double* x, SeriesDev* s, const int64_t* seg_bounds_dev, 
 size_t stats_job_bytes() { return sizeof(StatsJobDev); }
 
 void stats_carve_job(Arena& a, const double* x_dev, int64_t n, int32_t m, SeriesDev* s, unsigned long long* clear,
-                     void* job_host, int64_t* blk_sum, int64_t* blk_loc, int64_t* blk_win)
+                     void* job_host, int64_t* blk_sum, int64_t* blk_loc, int64_t* blk_win, const int64_t* bounds_dev,
+                     int32_t n_seg)
 {
     stats_carve(a, n, m, s);
     StatsJobDev J = {};
@@ -539,6 +550,8 @@ void stats_carve_job(Arena& a, const double* x_dev, int64_t n, int32_t m, Series
     J.scal = s->scal;
     J.first = s->first;
     J.clear = clear;
+    J.bounds = bounds_dev;
+    J.n_seg = bounds_dev ? n_seg : 0;
     J.blk_sum = *blk_sum;
     J.blk_loc = *blk_loc;
     J.blk_win = *blk_win;

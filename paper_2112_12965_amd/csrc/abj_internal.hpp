@@ -148,6 +148,9 @@ struct Fp32Slot {
     int64_t WB;
     const int32_t* chunks;  // reference column chunks [c0, c1) (device)
     unsigned long long* keys;
+    // when set, tiles store their row keys here (one WA-entry row per chunk,
+    // no atomics) and the row epilogue reduces them; else atomicMax into keys
+    unsigned long long* part;
     int64_t tile0;
     int64_t nbands, nchunks;
     int64_t pairs;  // valid pairs (for timing records)
@@ -173,6 +176,9 @@ size_t fp32_lds_bytes(int max_m);
 // atomic tile counter); writes one packed (score, group) key per query row.
 // self: the slots are self-joins whose excl fields are honoured.
 // counter_zeroed: the caller already cleared the tile counter on the stream.
+// Bytes of the tile counters of one FP32 launch (zero before the launch).
+constexpr int kTileQueues = 16;
+constexpr size_t kTileCounterBytes = kTileQueues * 128;
 int join_fp32_batch(const Fp32Slot* slots_dev, int nslots, int64_t ntiles, int max_m, int64_t pairs,
                     unsigned long long* counter_dev, hipStream_t stream, bool self = false,
                     bool counter_zeroed = false);
@@ -181,8 +187,17 @@ int join_fp32_batch(const Fp32Slot* slots_dev, int nslots, int64_t ntiles, int m
 // (optional) receives the same values unrounded.  excl >= 0 makes it a
 // self-join epilogue: the flat conventions then only take reference windows
 // outside |j - i| <= excl.  pearson: report 1 - d^2 / (2m) instead of d.
+// part / nparts: per-chunk keys of the tiles (Fp32Slot::part), reduced here
+// instead of reading `keys`.
 int finalize_launch(const SeriesDev& A, const SeriesDev& B, const unsigned long long* keys, float* P, int64_t* I,
-                    hipStream_t stream, double* P64 = nullptr, int64_t excl = -1, bool pearson = false);
+                    hipStream_t stream, double* P64 = nullptr, int64_t excl = -1, bool pearson = false,
+                    const unsigned long long* part = nullptr, int nparts = 0);
+
+// Bytes of per-chunk keys for a join of WA rows over `nchunks` column chunks,
+// or 0 when the join should combine its tiles with atomics instead (many
+// chunks: the buffer would be large and the atomics are spread over a long
+// launch anyway).
+size_t fp32_partial_bytes(int64_t WA, int64_t nchunks);
 
 // Row epilogues of many joins in one launch (a serving batch): one descriptor
 // per join (finalize_job_bytes() bytes, AB-join conventions), blocks counted in *blk.
@@ -225,7 +240,8 @@ size_t query_scratch_bytes(int64_t n, int32_t m, int64_t WB, const abj_opts& o, 
 // Query-side join against reference statistics B: query statistics, pair loop
 // of the selected tier, row epilogue.  All scratch comes from `ar`.
 int join_query(const double* query, int64_t n, int32_t m, const SeriesDev& B, const abj_opts& o,
-               const MfmaPlan& plan, float* P, int64_t* I, Arena& ar, hipStream_t stream);
+               const MfmaPlan& plan, float* P, int64_t* I, Arena& ar, hipStream_t stream,
+               size_t part_bytes = 0);
 
 // Benchmark timing hooks (no-ops unless abj_profile_enable(1) was called):
 // prof_begin records a start event on the stream, prof_end the stop event and

@@ -159,18 +159,18 @@ size_t query_scratch_bytes(int64_t n, int32_t m, int64_t WB, const abj_opts& o, 
     const int64_t W = n - m + 1;
     size_t b = stats_scratch_bytes(n, W);
     b += al256(sizeof(unsigned long long) * (size_t)W);  // keys
-    // upload region: statistics job, slot descriptor, tile counter
-    b += al256(stats_job_bytes()) + al256(sizeof(Fp32Slot)) + 256;
+    // upload region: statistics job, slot descriptor, tile counters
+    b += al256(stats_job_bytes()) + al256(sizeof(Fp32Slot)) + kTileCounterBytes;
     if (o.tier != ABJ_TIER_FP32) b += mfma_scratch_bytes(plan);
     return b;
 }
 
 size_t pair_scratch_bytes(int64_t n_query, int64_t n_ref, int32_t n_seg, int32_t m, const abj_opts& o,
-                          const MfmaPlan& plan)
+                          const MfmaPlan& plan, size_t part_bytes)
 {
     const int64_t WB = n_ref >= m ? n_ref - m + 1 : 0;
     return stats_scratch_bytes(n_ref, WB) + fp32_chunk_bytes(n_seg, n_ref) + al256(stats_job_bytes()) +
-           query_scratch_bytes(n_query, m, WB, o, plan);
+           query_scratch_bytes(n_query, m, WB, o, plan) + part_bytes;
 }
 
 // The whole path of one join: the statistics of the query (and of the
@@ -179,9 +179,10 @@ size_t pair_scratch_bytes(int64_t n_query, int64_t n_ref, int32_t n_seg, int32_t
 // descriptors, the reference's segment bounds and chunk list and the zeroed
 // tile counter are built on the host and uploaded in one copy; the
 // per-window statistics pass clears the FP32 keys.
+// part_bytes: per-chunk keys (fp32_partial_bytes, reserved by the caller) or 0.
 int join_run(const double* query, int64_t n, int32_t m, const double* ref, int64_t n_ref, const int64_t* ref_bounds,
              int32_t n_seg, const SeriesDev* Bres, const abj_opts& o, const MfmaPlan& plan, float* P, int64_t* I,
-             Arena& ar, hipStream_t stream)
+             Arena& ar, hipStream_t stream, size_t part_bytes = 0)
 {
     const bool fp32 = o.tier == ABJ_TIER_FP32;
     const bool pearson = (o.flags & ABJ_FLAG_PEARSON) != 0;
@@ -194,7 +195,7 @@ int join_run(const double* query, int64_t n, int32_t m, const double* ref, int64
     const size_t o_jobs = al256(o_chunks + sizeof(int32_t) * chunks.size());
     const size_t o_slot = o_jobs + al256(jb * (size_t)njobs);
     const size_t o_counter = o_slot + al256(sizeof(Fp32Slot));
-    const size_t up = o_counter + 256;
+    const size_t up = o_counter + kTileCounterBytes;
     char* U = ar.take<char>(up);
     std::vector<char> h(up, 0);
     int64_t bs = 0, bl = 0, bw = 0;
@@ -219,8 +220,13 @@ int join_run(const double* query, int64_t n, int32_t m, const double* ref, int64
     stats_carve_job(ar, query, n, m, &A, fp32 ? keys : nullptr, h.data() + o_jobs + (size_t)(njobs - 1) * jb, &bs,
                     &bl, &bw);
     Fp32Slot sl = {};
+    unsigned long long* part = nullptr;
     if (fp32) {
         fp32_slot(A, B, keys, 0, &sl);
+        if (part_bytes && part_bytes == fp32_partial_bytes(A.W, sl.nchunks)) {
+            part = ar.take<unsigned long long>(part_bytes / sizeof(unsigned long long));
+            sl.part = part;
+        }
         memcpy(h.data() + o_slot, &sl, sizeof(sl));
     }
     ABJ_HIP(hipMemcpyAsync(U, h.data(), up, hipMemcpyHostToDevice, stream));
@@ -229,13 +235,13 @@ int join_run(const double* query, int64_t n, int32_t m, const double* ref, int64
         return join_mfma_run(A, B, plan, !(o.flags & ABJ_FLAG_NO_REFINE), pearson, P, I, ar, stream);
     ABJ_TRY(join_fp32_batch(reinterpret_cast<const Fp32Slot*>(U + o_slot), 1, fp32_slot_tiles(sl), m, sl.pairs,
                             reinterpret_cast<unsigned long long*>(U + o_counter), stream, false, true));
-    return finalize_launch(A, B, keys, P, I, stream, nullptr, -1, pearson);
+    return finalize_launch(A, B, keys, P, I, stream, nullptr, -1, pearson, part, part ? (int)sl.nchunks : 0);
 }
 
 int join_query(const double* query, int64_t n, int32_t m, const SeriesDev& B, const abj_opts& o,
-               const MfmaPlan& plan, float* P, int64_t* I, Arena& ar, hipStream_t stream)
+               const MfmaPlan& plan, float* P, int64_t* I, Arena& ar, hipStream_t stream, size_t part_bytes)
 {
-    return join_run(query, n, m, nullptr, 0, nullptr, 0, &B, o, plan, P, I, ar, stream);
+    return join_run(query, n, m, nullptr, 0, nullptr, 0, &B, o, plan, P, I, ar, stream, part_bytes);
 }
 
 int stats_export(const SeriesDev& s, double* mu, double* sig, uint8_t* flags, hipStream_t stream);
@@ -336,7 +342,12 @@ extern "C" int ab_join(const double* query, int64_t n_query, const double* dict,
 
     hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
     Arena ar(stream);
-    ar.reserve(pair_scratch_bytes(n_query, n_dict, n_seg, m, o, plan));
+    // per-chunk keys instead of atomics when the chunk list is short
+    size_t part_bytes = 0;
+    if (o.tier == ABJ_TIER_FP32 && WB > 0)
+        part_bytes = fp32_partial_bytes(WA, (int64_t)fp32_chunk_list(seg_bounds, n_seg, n_dict, m).size() / 2);
+    ar.reserve(pair_scratch_bytes(n_query, n_dict, n_seg, m, o, plan, part_bytes));
     ABJ_TRY(ar.commit());
-    return join_run(query, n_query, m, dict, n_dict, seg_bounds, n_seg, nullptr, o, plan, P_AB, I_AB, ar, stream);
+    return join_run(query, n_query, m, dict, n_dict, seg_bounds, n_seg, nullptr, o, plan, P_AB, I_AB, ar, stream,
+                    part_bytes);
 }

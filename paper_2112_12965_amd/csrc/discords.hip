@@ -181,7 +181,7 @@ extern "C" int discords(const double* query, int64_t n_query, int32_t m, const f
     ar.reserve((size_t)nb);                              // band flags
     ar.reserve(sizeof(unsigned long long) * (size_t)(KK + 4));
     ar.reserve(sizeof(Fp32Slot) * (size_t)nb);
-    ar.reserve(sizeof(unsigned long long));               // tile counter
+    ar.reserve(kTileCounterBytes);                        // tile counters
     ABJ_TRY(ar.commit());
     SeriesDev B, A;
     stats_carve(ar, n_ref, m, &B);
@@ -203,7 +203,7 @@ extern "C" int discords(const double* query, int64_t n_query, int32_t m, const f
     uint8_t* bflag = ar.take<uint8_t>((size_t)nb);
     unsigned long long* pk = ar.take<unsigned long long>((size_t)(KK + 4));
     Fp32Slot* dslots = ar.take<Fp32Slot>((size_t)nb);
-    unsigned long long* counter = ar.take<unsigned long long>(1);
+    unsigned long long* counter = ar.take<unsigned long long>(kTileCounterBytes / 8);
 
     ABJ_HIP(hipMemcpyAsync(Pmix, P_hat, sizeof(float) * (size_t)W, hipMemcpyDeviceToDevice, stream));
     hipLaunchKernelGGL(k_fill_i64, dim3(grid_of(W)), dim3(kBlock), 0, stream, Iex, W, (int64_t)-1);

@@ -75,7 +75,7 @@ __device__ __forceinline__ void finalize_body(
     const double* __restrict__ bsig, const unsigned long long* __restrict__ bfirst,
     const uint8_t* __restrict__ bflags, int64_t WB, int m, int64_t excl, int pearson,
     const unsigned long long* __restrict__ keys, float* __restrict__ P, int64_t* __restrict__ I,
-    double* __restrict__ P64, int64_t blk)
+    double* __restrict__ P64, int64_t blk, const unsigned long long* __restrict__ part = nullptr, int nparts = 0)
 {
     __shared__ float stage_all[kWavesPerBlock][kStage];
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
@@ -90,7 +90,22 @@ __device__ __forceinline__ void finalize_body(
     const int64_t ic = i < WA ? i : WA - 1;  // rows past the end read a valid row and are masked
     // flags and key together (one memory round trip)
     const uint8_t fa = i < WA ? aflags[ic] : (uint8_t)kFlagBad;
-    const unsigned long long key = keys ? keys[ic] : 0ull;
+    unsigned long long key = 0ull;
+    if (part) {
+        // the row's key is the largest of its tiles' keys: lane c takes
+        // chunks c, c + 16, ..., then the row's 16 lanes combine
+        for (int p = c; p < nparts; p += kGroup) {
+            const unsigned long long v = part[(int64_t)p * WA + ic];
+            key = v > key ? v : key;
+        }
+#pragma unroll
+        for (int off = 1; off < kGroup; off <<= 1) {
+            const unsigned long long o = __shfl_xor(key, off, kWave);
+            key = o > key ? o : key;
+        }
+    } else if (keys) {
+        key = keys[ic];
+    }
     int64_t jb = -1;
     if (i < WA && key && !(fa & (kFlagBad | kFlagFlat))) jb = (int64_t)(0xFFFFFFFFu - (unsigned)(key & 0xFFFFFFFFull));
     int64_t jrows[kRowsPerWave];
@@ -304,10 +319,10 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
     const double* __restrict__ bsig, const unsigned long long* __restrict__ bfirst,
     const uint8_t* __restrict__ bflags, int64_t WB, int m, int64_t excl, int pearson,
     const unsigned long long* __restrict__ keys, float* __restrict__ P, int64_t* __restrict__ I,
-    double* __restrict__ P64)
+    double* __restrict__ P64, const unsigned long long* __restrict__ part, int nparts)
 {
     finalize_body(axc, amu, asig, aflags, WA, bxc, bmu, bsig, bfirst, bflags, WB, m, excl, pearson, keys, P, I, P64,
-                  blockIdx.x);
+                  blockIdx.x, part, nparts);
 }
 
 // Many joins per launch (a serving batch); workgroups never mix joins, so the
@@ -346,13 +361,15 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
 }  // namespace
 
 int finalize_launch(const SeriesDev& A, const SeriesDev& B, const unsigned long long* keys, float* P, int64_t* I,
-                    hipStream_t stream, double* P64, int64_t excl, bool pearson)
+                    hipStream_t stream, double* P64, int64_t excl, bool pearson, const unsigned long long* part,
+                    int nparts)
 {
     if (A.W <= 0) return ABJ_OK;
     const int64_t rows_per_block = (int64_t)kWavesPerBlock * kRowsPerWave;
     const int64_t g = (A.W + rows_per_block - 1) / rows_per_block;
     hipLaunchKernelGGL(k_finalize, dim3((unsigned)g), dim3(kWave * kWavesPerBlock), 0, stream, A.xc, A.mu, A.sig,
-                       A.flags, A.W, B.xc, B.mu, B.sig, B.first, B.flags, B.W, (int)A.m, excl, pearson ? 1 : 0, keys, P, I, P64);
+                       A.flags, A.W, B.xc, B.mu, B.sig, B.first, B.flags, B.W, (int)A.m, excl, pearson ? 1 : 0, keys, P,
+                       I, P64, part, nparts);
     ABJ_HIP(hipGetLastError());
     return ABJ_OK;
 }

@@ -309,16 +309,29 @@ __device__ __forceinline__ void join_tile(const Fp32Slot& sl, int64_t band, int6
             sweep_block<true, kExcl>(jb, jend, bcol, e, S, pf, pg, best, bidx, prev, ibase, sl.excl);
         }
     }
+    if (sl.part) {
+        // every tile writes each of its rows once: plain stores, no atomics
+        unsigned long long* __restrict__ pc = sl.part + chunk * WA;
 #pragma unroll
-    for (int r = 0; r < kR; ++r) {
-        const int64_t i = ibase + r;
-        if (i < WA && best[r] > -INFINITY) atomicMax(&keys[i], pack_key(best[r], bidx[r]));
+        for (int r = 0; r < kR; ++r) {
+            const int64_t i = ibase + r;
+            if (i < WA) pc[i] = best[r] > -INFINITY ? pack_key(best[r], bidx[r]) : 0ull;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < kR; ++r) {
+            const int64_t i = ibase + r;
+            if (i < WA && best[r] > -INFINITY) atomicMax(&keys[i], pack_key(best[r], bidx[r]));
+        }
     }
 }
 
-// Persistent batch kernel: every workgroup (one wave) takes tiles from the
-// launch's list through one atomic counter until the list is exhausted (the
-// list is finite, so every wave reaches the exit).  Tiles of different slots
+// Persistent batch kernel: workgroup w (one wave) first joins tile w, then
+// takes tiles from one of kTileQueues interleaved queues of the rest (queue q
+// holds tiles grid + q + kTileQueues k; its counter sits on a line of its
+// own), so that no single counter serialises the launch.  Device-wide atomics
+// are carried out beyond the XCDs' L2 caches, so contended ones cost tens of
+// nanoseconds each.  Every queue is finite, so every wave reaches the exit.  Tiles of different slots
 // (requests) with different lengths and window lengths share the launch.
 // kSelf: self-join launch; tiles that meet a slot's trivial-match zone take the
 // masked sweep (a separate instantiation, so the AB-join kernel carries none of it).
@@ -327,15 +340,10 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void
     const Fp32Slot* __restrict__ slots, int nslots, int64_t ntiles, unsigned long long* __restrict__ counter)
 {
     extern __shared__ double lds[];
-    for (;;) {
-        unsigned long long t = 0;
-        if (threadIdx.x == 0) t = atomicAdd(counter, 1ull);
-        // wave-uniform tile index in scalar registers, so that everything derived
-        // from it (slot, pointers, column loop) stays scalar
-        t = __shfl(t, 0, kWave);
-        const unsigned tlo = __builtin_amdgcn_readfirstlane((unsigned)t);
-        const unsigned thi = __builtin_amdgcn_readfirstlane((unsigned)(t >> 32));
-        t = ((unsigned long long)thi << 32) | tlo;
+    const unsigned long long grid = gridDim.x;
+    const unsigned q = blockIdx.x % kTileQueues;
+    unsigned long long* __restrict__ qc = counter + q * (128 / sizeof(unsigned long long));
+    for (unsigned long long t = blockIdx.x;;) {
         if (t >= (unsigned long long)ntiles) break;
         // slot holding tile t: the last slot whose first tile is <= t
         int lo = 0, hi = nslots;
@@ -360,6 +368,16 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void
             join_tile<false>(sl, band, chunk, lds);
         }
         __syncthreads();  // the next tile reuses the LDS buffers
+        // next tile of this wave's queue
+        if (grid + q >= (unsigned long long)ntiles) break;  // the queue is empty
+        unsigned long long k = 0;
+        if (threadIdx.x == 0) k = atomicAdd(qc, 1ull);
+        // wave-uniform tile index in scalar registers, so that everything derived
+        // from it (slot, pointers, column loop) stays scalar
+        k = __shfl(k, 0, kWave);
+        const unsigned klo = __builtin_amdgcn_readfirstlane((unsigned)k);
+        const unsigned khi = __builtin_amdgcn_readfirstlane((unsigned)(k >> 32));
+        t = grid + q + kTileQueues * (((unsigned long long)khi << 32) | klo);
     }
 }
 
@@ -377,6 +395,7 @@ void fp32_slot(const SeriesDev& A, const SeriesDev& B, unsigned long long* keys,
     sl->WB = B.W;
     sl->m = A.m;
     sl->keys = keys;
+    sl->part = nullptr;
     sl->tile0 = tile0;
     sl->nbands = A.W > 0 ? (A.W + kBandRows - 1) / kBandRows : 0;
     sl->chunks = B.chunks;
@@ -386,6 +405,13 @@ void fp32_slot(const SeriesDev& A, const SeriesDev& B, unsigned long long* keys,
 }
 
 int64_t fp32_slot_tiles(const Fp32Slot& sl) { return sl.nbands * sl.nchunks; }
+
+size_t fp32_partial_bytes(int64_t WA, int64_t nchunks)
+{
+    if (WA <= 0 || nchunks <= 1 || nchunks > 64) return 0;
+    const size_t b = sizeof(unsigned long long) * (size_t)WA * (size_t)nchunks;
+    return b <= ((size_t)256 << 20) ? (b + 255) & ~size_t(255) : 0;
+}
 
 size_t fp32_chunk_bytes(int32_t n_seg, int64_t n)
 {
@@ -442,7 +468,7 @@ int join_fp32_batch(const Fp32Slot* slots_dev, int nslots, int64_t ntiles, int m
                     unsigned long long* counter_dev, hipStream_t stream, bool self, bool counter_zeroed)
 {
     if (ntiles <= 0) return ABJ_OK;
-    if (!counter_zeroed) ABJ_TRY(fill_u64(counter_dev, 1, 0ull, stream));
+    if (!counter_zeroed) ABJ_TRY(fill_u64(counter_dev, kTileCounterBytes / 8, 0ull, stream));
     // enough one-wave workgroups to fill every SIMD four deep, never more than tiles
     const int64_t grid = ntiles < 4096 ? ntiles : 4096;
     ProfMark mark;

@@ -355,13 +355,13 @@ extern "C" int self_join(const double* x, int64_t n, int32_t m, int64_t excl, fl
     ar.reserve(series_stats_bytes(n, W));
     ar.reserve(sizeof(unsigned long long) * (size_t)W);
     ar.reserve(sizeof(Fp32Slot));
-    ar.reserve(sizeof(unsigned long long));
+    ar.reserve(kTileCounterBytes);
     ABJ_TRY(ar.commit());
     SeriesDev T;
     ABJ_TRY(series_stats(x, n, m, ar, &T, stream));
     unsigned long long* keys = ar.take<unsigned long long>((size_t)W);
     Fp32Slot* dslot = ar.take<Fp32Slot>(1);
-    unsigned long long* counter = ar.take<unsigned long long>(1);
+    unsigned long long* counter = ar.take<unsigned long long>(kTileCounterBytes / 8);
     const bool pearson = opts && (opts->flags & ABJ_FLAG_PEARSON);
     return self_join_launch(T, excl, keys, dslot, counter, P, I, P64, stream, pearson);
 }
@@ -410,7 +410,7 @@ extern "C" int dict_build(const double* series, int64_t n, int32_t m, const abj_
     ar.reserve(series_stats_bytes(n, W));
     ar.reserve(sizeof(unsigned long long) * (size_t)W);  // keys
     ar.reserve(sizeof(Fp32Slot));
-    ar.reserve(sizeof(unsigned long long));               // tile counter
+    ar.reserve(kTileCounterBytes);                        // tile counters
     ar.reserve(sizeof(float) * (size_t)W);                // P
     ar.reserve(sizeof(int64_t) * (size_t)W);              // I
     ar.reserve(sizeof(double) * (size_t)W);               // P64
@@ -437,7 +437,7 @@ extern "C" int dict_build(const double* series, int64_t n, int32_t m, const abj_
     ABJ_TRY(series_stats(series, n, m, ar, &L.ts, stream));
     L.keys = ar.take<unsigned long long>((size_t)W);
     L.slot = ar.take<Fp32Slot>(1);
-    L.counter = ar.take<unsigned long long>(1);
+    L.counter = ar.take<unsigned long long>(kTileCounterBytes / 8);
     L.P = ar.take<float>((size_t)W);
     L.I = ar.take<int64_t>((size_t)W);
     L.P64 = ar.take<double>((size_t)W);

@@ -170,9 +170,12 @@ extern "C" int ab_join_dict(const abj_dict* d, const double* query, int64_t n_qu
     ABJ_TRY(ensure_device());
     hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
     Arena ar(stream);
-    ar.reserve(query_scratch_bytes(n_query, m, e->B.W, o, plan));
+    // per-chunk keys instead of atomics when the chunk list is short
+    const size_t part_bytes =
+        o.tier == ABJ_TIER_FP32 && e->B.W > 0 ? fp32_partial_bytes(WA, e->B.nchunks) : 0;
+    ar.reserve(query_scratch_bytes(n_query, m, e->B.W, o, plan) + part_bytes);
     ABJ_TRY(ar.commit());
-    return join_query(query, n_query, m, e->B, o, plan, P_AB, I_AB, ar, stream);
+    return join_query(query, n_query, m, e->B, o, plan, P_AB, I_AB, ar, stream, part_bytes);
 }
 
 // ---------------------------------------------------------------------------
@@ -347,7 +350,7 @@ int launch_batch(abj_server* s, Batch& b)
     const bool fp32 = s->jo.tier == ABJ_TIER_FP32;
     const size_t t_stats = al256(stats_job_bytes() * k), t_slots = al256(sizeof(Fp32Slot) * k),
                  t_fin = al256(finalize_job_bytes() * k);
-    const size_t tables = fp32 ? t_stats + t_slots + t_fin + 256 : 0;
+    const size_t tables = fp32 ? t_stats + t_slots + t_fin + kTileCounterBytes : 0;
     size_t qbytes = 0, pbytes = 0, ibytes = 0, work = 0;
     for (Req* r : b.reqs) {
         qbytes += al256(sizeof(double) * (size_t)r->n);
@@ -358,7 +361,7 @@ int launch_batch(abj_server* s, Batch& b)
     const size_t up = tables + qbytes, down = pbytes + ibytes;
     const size_t slots = (size_t)s->o.max_slots;
     const size_t cap = (size_t)s->o.mem_budget + al256(stats_job_bytes() * slots) + al256(sizeof(Fp32Slot) * slots) +
-                       al256(finalize_job_bytes() * slots) + 256;
+                       al256(finalize_job_bytes() * slots) + kTileCounterBytes;
     ABJ_TRY(grow_device(&sb.dev, &sb.dev_bytes, up + down + work, cap, st));
     ABJ_TRY(grow_pinned(s, &sb.hin, &sb.hin_bytes, up));
     {
@@ -407,12 +410,13 @@ int launch_batch(abj_server* s, Batch& b)
         finalize_job(r->A, r->dm->B, r->keys, r->dP, r->dI, H + t_stats + t_slots + a * finalize_job_bytes(),
                      &blk_fin);
     }
-    if (fp32) memset(H + tables - 256, 0, 256);  // tile counter
+    if (fp32) memset(H + tables - kTileCounterBytes, 0, kTileCounterBytes);  // tile counters
     ABJ_HIP(hipMemcpyAsync(D, H, up, hipMemcpyHostToDevice, st));
     if (fp32) {
         ABJ_TRY(stats_launch_many(D, (int)k, blk_sum, blk_loc, blk_win, st));
         ABJ_TRY(join_fp32_batch(reinterpret_cast<const Fp32Slot*>(D + t_stats), (int)k, tiles, max_m, pairs,
-                                reinterpret_cast<unsigned long long*>(D + tables - 256), st, false, true));
+                                reinterpret_cast<unsigned long long*>(D + tables - kTileCounterBytes), st, false,
+                                true));
         ABJ_TRY(finalize_launch_many(D + t_stats + t_slots, (int)k, blk_fin, st));
     } else {
         for (Req* r : b.reqs) {

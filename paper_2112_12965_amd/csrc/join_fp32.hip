@@ -50,26 +50,44 @@ constexpr int kQ = kTC / kWave;         // top-edge columns per lane
 constexpr int kDppWaveShr1 = 0x138;     // DPP control: whole-wave shift right by one lane
 constexpr int kG = 16;                  // width of the FP64 edge dot-product groups
 
-// acc[g] = sum_{k<m} w[k] * x[base + g + k] for g < G.  x is read through a
-// G-entry register window that slides by one sample per k (one load per G FMAs).
-template <int G, typename Ptr>
-__device__ inline void sliding_dots(Ptr __restrict__ x, int64_t base, const double* w, int m, double (&acc)[G])
+// The slot's arrays live in global memory; saying so keeps their loads global
+// (not flat) although the pointers come from a descriptor in memory.
+typedef double vd2 __attribute__((ext_vector_type(2)));
+typedef const __attribute__((address_space(1))) double* GDbl;
+typedef const __attribute__((address_space(1))) vd2* GVd2;
+
+// acc[g] = sum_{k<m} w[k] * x[base + g + k] for g < G, for an even `base`
+// (x + base is 16-byte aligned).  x is read through a G-entry register window
+// that slides by one sample per k and is refilled two samples per load (one
+// load per 2G FMAs; a wave-wide load touches one cache line per lane, since
+// the lanes' windows are 16 samples apart, so fewer loads is what counts).
+template <int G>
+__device__ inline void sliding_dots_even(GDbl __restrict__ x, int64_t base, const double* w, int m, double (&acc)[G])
 {
+    static_assert(G % 2 == 0, "pairs");
+    GVd2 __restrict__ xp = (GVd2)(x + base);
     double win[G];
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
+    for (int g = 0; g < G; g += 2) {
+        const vd2 v = xp[g / 2];
+        win[g] = v.x;
+        win[g + 1] = v.y;
         acc[g] = 0.0;
-        win[g] = x[base + g];
+        acc[g + 1] = 0.0;
     }
     int k0 = 0;
     // Invariant at the top of each block: win[s] holds x[base + k0 + s].
     for (; k0 + G <= m; k0 += G) {
 #pragma unroll
-        for (int kk = 0; kk < G; ++kk) {
-            const double wk = w[k0 + kk];
+        for (int kk = 0; kk < G; kk += 2) {
+            const vd2 nx = xp[(k0 + kk + G) / 2];
+            const double w0 = w[k0 + kk], w1 = w[k0 + kk + 1];
 #pragma unroll
-            for (int g = 0; g < G; ++g) acc[g] = fma(wk, win[(kk + g) % G], acc[g]);
-            win[kk] = x[base + k0 + kk + G];
+            for (int g = 0; g < G; ++g) acc[g] = fma(w0, win[(kk + g) % G], acc[g]);
+            win[kk] = nx.x;
+#pragma unroll
+            for (int g = 0; g < G; ++g) acc[g] = fma(w1, win[(kk + 1 + g) % G], acc[g]);
+            win[kk + 1] = nx.y;
         }
     }
     for (int k = k0; k < m; ++k) {
@@ -91,9 +109,6 @@ __device__ inline double wave_sum(double v)
 typedef float vf4 __attribute__((ext_vector_type(4)));  // same layout as float4
 typedef float vf2 __attribute__((ext_vector_type(2)));  // same layout as float2
 typedef const __attribute__((address_space(4))) vf4* ColPtr;
-// The slot's arrays live in global memory; saying so keeps their loads global
-// (not flat) although the pointers come from a descriptor in memory.
-typedef const __attribute__((address_space(1))) double* GDbl;
 typedef const __attribute__((address_space(1))) vf2* GVf2;
 
 __host__ __device__ inline size_t edge_offset(int m) { return ((size_t)m * sizeof(double) + 15) & ~size_t(15); }
@@ -219,7 +234,7 @@ __device__ __forceinline__ void join_tile(const Fp32Slot& sl, int64_t band, int6
         for (int h = 0; h < kQ; h += kG) {
             if (cbase + h >= jend) break;  // columns past the chunk are never swept
             double acc[kG];
-            sliding_dots<kG>(bxc, cbase + h, wv, m, acc);
+            sliding_dots_even<kG>(bxc, cbase + h, wv, m, acc);  // j0 is even
 #pragma unroll
             for (int g = 0; g < kG; ++g) {
                 const int64_t j = cbase + h + g;
@@ -247,7 +262,7 @@ __device__ __forceinline__ void join_tile(const Fp32Slot& sl, int64_t band, int6
 #pragma unroll
         for (int h = 0; h < kR; h += kG) {
             double acc[kG];
-            sliding_dots<kG>(axc, ibase + h, wv, m, acc);
+            sliding_dots_even<kG>(axc, ibase + h, wv, m, acc);  // i0 is a multiple of 1024
 #pragma unroll
             for (int g = 0; g < kG; ++g) {
                 const int64_t i = ibase + h + g;
@@ -424,6 +439,13 @@ std::vector<int32_t> fp32_chunk_list(const int64_t* bounds, int32_t n_seg, int64
 {
     std::vector<int32_t> c;
     auto split = [&](int64_t a, int64_t cnt) {
+        // chunks start at even columns (16-byte aligned samples for the edge
+        // loads): an odd segment start takes the column before it along, a
+        // window that crosses the break and so carries the -inf bias
+        if (a & 1) {
+            --a;
+            ++cnt;
+        }
         // equal widths, a multiple of 16 except the last, so that no tile is a sliver
         const int64_t k = (cnt + kTC - 1) / kTC;
         int64_t w = (cnt + k - 1) / k;

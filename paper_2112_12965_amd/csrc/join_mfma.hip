@@ -138,6 +138,17 @@ __device__ inline void topk_insert(float (&tv)[K], int (&ti)[K], float v, int j)
         }
 }
 
+// Largest of 16 values (NaN-free inputs; the compiler forms max3 chains).
+__device__ inline float max16(const float (&a)[16])
+{
+    const float m0 = fmaxf(fmaxf(a[0], a[1]), a[2]);
+    const float m1 = fmaxf(fmaxf(a[3], a[4]), a[5]);
+    const float m2 = fmaxf(fmaxf(a[6], a[7]), a[8]);
+    const float m3 = fmaxf(fmaxf(a[9], a[10]), a[11]);
+    const float m4 = fmaxf(fmaxf(a[12], a[13]), a[14]);
+    return fmaxf(fmaxf(fmaxf(fmaxf(m0, m1), m2), fmaxf(m3, m4)), a[15]);
+}
+
 // Row index (within the 32-window block) of accumulator v in lane `lane`.
 __device__ inline int acc_row(int v, int lane) { return 8 * (v / 4) + 4 * (lane / 32) + (v % 4); }
 
@@ -245,25 +256,35 @@ __global__ __launch_bounds__(kWave* waves_per_block(KS)) __attribute__((amdgpu_w
                     float a[16];
 #pragma unroll
                     for (int v = 0; v < 16; ++v) a[v] = acc[h][nb][v];
-                    if (msk[h] != 0xFFFFFFFFu) {
+                    if (__builtin_expect(msk[h] != 0xFFFFFFFFu, 0)) {
+                        // a block that straddles a segment break (rare): the
+                        // opaque copy keeps the per-lane tests inside the branch
+                        uint32_t mm = msk[h];
+                        asm volatile("" : "+s"(mm));
 #pragma unroll
                         for (int v = 0; v < 16; ++v)
-                            if (!((msk[h] >> acc_row(v, lane)) & 1u)) a[v] = -INFINITY;
+                            if (!((mm >> acc_row(v, lane)) & 1u)) a[v] = -INFINITY;
                     }
-                    const float m0 = fmaxf(fmaxf(a[0], a[1]), a[2]);
-                    const float m1 = fmaxf(fmaxf(a[3], a[4]), a[5]);
-                    const float m2 = fmaxf(fmaxf(a[6], a[7]), a[8]);
-                    const float m3 = fmaxf(fmaxf(a[9], a[10]), a[11]);
-                    const float m4 = fmaxf(fmaxf(a[12], a[13]), a[14]);
-                    const float mx = fmaxf(fmaxf(fmaxf(fmaxf(m0, m1), m2), fmaxf(m3, m4)), a[15]);
-                    const bool hit = mx > tv[nb][K - 1];
+                    float mx = max16(a);
+                    bool hit = mx > tv[nb][K - 1];
                     if (__builtin_expect(__builtin_amdgcn_ballot_w64(hit) != 0, 0)) {
+                        // rare (a row's K-th best improves a few dozen times per
+                        // chunk): insert the lane's largest value above its K-th
+                        // best, one per pass, until no lane of the wave has one
                         asm volatile("" ::: "memory");
-                        if (hit) {
+                        do {
+                            if (hit) {
+                                // first (smallest row) position of the lane's largest value
+                                int sel = 0;
 #pragma unroll
-                            for (int v = 0; v < 16; ++v)
-                                topk_insert<K>(tv[nb], ti[nb], a[v], jbase + acc_row(v, lane));
-                        }
+                                for (int v = 15; v >= 0; --v) sel = a[v] == mx ? v : sel;
+                                topk_insert<K>(tv[nb], ti[nb], mx, jbase + acc_row(sel, lane));
+#pragma unroll
+                                for (int v = 0; v < 16; ++v) a[v] = v == sel ? -INFINITY : a[v];
+                                mx = max16(a);
+                                hit = mx > tv[nb][K - 1];
+                            }
+                        } while (__builtin_amdgcn_ballot_w64(hit) != 0);
                     }
                 }
             }

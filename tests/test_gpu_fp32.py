@@ -64,6 +64,19 @@ def test_multi_tile_ragged_segments(orc, m):
     full_check(orc, q, d, bounds, m)
 
 
+@pytest.mark.parametrize("n_seg", [63, 64, 65, 70])
+def test_many_segments_both_merges(orc, n_seg):
+    # up to 64 column chunks the tiles store per-chunk keys that the epilogue
+    # reduces; beyond that they merge with atomics: both sides of the switch
+    rng = np.random.default_rng(2000 + n_seg)
+    m = 16
+    lens = rng.integers(40, 80, n_seg)
+    d = synth.random_walk(int(lens.sum()), rng)
+    bounds = np.concatenate([[0], np.cumsum(lens)]).tolist()
+    q = synth.random_walk(2500, rng)
+    full_check(orc, q, d, bounds, m)
+
+
 def test_ecg_dictionary_m256(orc):
     rng = synth.rng_for(91, 0)
     q = synth.ecg_like(4096, rng, n_anomalies=3)

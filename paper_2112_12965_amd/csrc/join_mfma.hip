@@ -431,7 +431,9 @@ void launch_main(const MfmaPlan& p, const void* zq, const void* zd, const uint32
                  unsigned long long* cand, hipStream_t stream)
 {
     using V8 = typename Vec8<T>::type;
-    constexpr int WPE = 2;  // two waves per SIMD
+    // four waves per SIMD where the 8-wave workgroup's 64 KB of LDS allows two
+    // workgroups per CU; the 4-wave workgroups of K-step 16 fit two per SIMD
+    constexpr int WPE = KS <= 8 ? 4 : 2;
     hipLaunchKernelGGL((k_join_mfma<T, KS, NB, K, WPE>), dim3((unsigned)(p.npanels * p.nchunks)),
                        dim3(kWave * waves_per_block(KS)), 0, stream, reinterpret_cast<const V8*>(zq), p.nqblk,
                        reinterpret_cast<const V8*>(zd), dmask, p.ndblk, p.npanels, p.blk_per_chunk,
@@ -457,9 +459,9 @@ int launch_ks(const MfmaPlan& p, const void* zq, const void* zd, const uint32_t*
               hipStream_t stream)
 {
     switch (p.KS) {
-        case 2: return launch_k<T, 2, 2>(p, zq, zd, dmask, cand, stream);
-        case 4: return launch_k<T, 4, 2>(p, zq, zd, dmask, cand, stream);
-        case 8: return launch_k<T, 8, 2>(p, zq, zd, dmask, cand, stream);
+        case 2: return launch_k<T, 2, 1>(p, zq, zd, dmask, cand, stream);
+        case 4: return launch_k<T, 4, 1>(p, zq, zd, dmask, cand, stream);
+        case 8: return launch_k<T, 8, 1>(p, zq, zd, dmask, cand, stream);
         case 16: return launch_k<T, 16, 1>(p, zq, zd, dmask, cand, stream);
         default: return set_error(ABJ_EINVAL, "unsupported k-step count %d", p.KS);
     }
@@ -487,7 +489,9 @@ int mfma_plan(int64_t WA, int64_t WB, int32_t m, int tier, int refine_k, MfmaPla
     else return set_error(ABJ_EINVAL, "the BF16/FP16 tiers support m <= 256 (got %d)", m);
     int K = refine_k <= 0 ? 4 : refine_k;
     K = K <= 1 ? 1 : K <= 2 ? 2 : K <= 4 ? 4 : 8;
-    const int NB = KS <= 8 ? 2 : 1;  // query blocks per wave (register budget)
+    // one query block per wave: it leaves the registers for four waves per
+    // SIMD (K-steps <= 8), which hide the LDS and MFMA latencies of the sweep
+    const int NB = 1;
     p->tier = tier;
     p->KS = KS;
     p->K = K;

@@ -92,6 +92,51 @@ def cpu_baseline(w, results, target_s: float, threads: int):
     )
 
 
+def short_windows(abjoin, synth, ms=(16, 32, 64), n=262144, rows=192):
+    """Tiers against short windows: whole-step pairs/s of every tier on two
+    n-sample random walks per m.  Returns the record and, for the CPU leg's
+    error check, each tier's result on `rows` random query rows."""
+    import torch
+
+    rng = synth.rng_for(7, 0)
+    a_h, b_h = synth.random_walk(n, rng), synth.random_walk(n, rng)
+    a, b = torch.from_numpy(a_h).cuda(), torch.from_numpy(b_h).cuda()
+    out = {"workload": f"random walks {n} x {n}", "m": {}}
+    samples = {}
+    for m in ms:
+        W = n - m + 1
+        rec = {}
+        sample = np.sort(np.random.default_rng(100 + m).choice(W, rows, replace=False))
+        got = {}
+        for tier in ("fp32", "bf16", "fp16"):
+            P = torch.empty(W, dtype=torch.float32, device="cuda")
+            I = torch.empty(W, dtype=torch.int64, device="cuda")
+            dt = time_tier(abjoin, a, b, [0, n], m, tier, 5, 2, P, I)
+            rec[tier] = {"pairs_per_s": W * W / dt, "ms_per_step": dt * 1e3}
+            got[tier] = (P.cpu().numpy().astype(np.float64)[sample], I.cpu().numpy()[sample])
+        for tier in ("bf16", "fp16"):
+            rec[tier]["vs_fp32"] = rec[tier]["pairs_per_s"] / rec["fp32"]["pairs_per_s"]
+        out["m"][str(m)] = rec
+        samples[m] = (sample, got)
+    return out, (a_h, b_h, samples)
+
+
+def short_window_errors(record, data, threads):
+    """Each tier's error on the sampled rows against the FP64 oracle (CPU leg)."""
+    import oracle
+
+    a_h, b_h, samples = data
+    n = len(a_h)
+    for m, (rows, got) in samples.items():
+        Po, Io, P2o = oracle.ab_join(a_h, b_h, [0, n], m, rows=rows, threads=threads, second=True)
+        clear = (P2o - Po) > 1e-3
+        for tier, (Pg, Ig) in got.items():
+            r = record["m"][str(m)][tier]
+            r["rows_checked"] = int(len(rows))
+            r["max_abs_err"] = float(np.abs(Pg - Po).max())
+            r["index_match_clear_rows"] = float(np.mean(Ig[clear] == Io[clear])) if clear.any() else 1.0
+
+
 def time_tier(abjoin, q, d, bounds, m, tier, steps, warmup, P, I):
     import torch
 
@@ -252,11 +297,15 @@ def main():
             out["tiers"][tier] = {"pairs_per_s": pairs / dtt, "ms_per_step": dtt * 1e3,
                                   "vs_fp32": (pairs / dtt) / out["value"]}
             results[tier] = (Pt.cpu().numpy(), It.cpu().numpy())
+        # the precision tier against the FP32 tier where its O(m) products are short
+        out["tiers_short_windows"], short_data = short_windows(abjoin, synth)
     if not args.no_cpu:
         threads = min(16, os.cpu_count() or 1)
         cb, errs = cpu_baseline(w, results, args.cpu_seconds, threads)
         out["cpu_baseline"] = cb
         out["error_vs_oracle"] = errs
+        if not args.no_tiers:
+            short_window_errors(out["tiers_short_windows"], short_data, threads)
     if not args.no_serving:
         out["serving"] = serving(abjoin, synth, ("fp32", "bf16"), args.serve_requests)
     print(json.dumps(out), flush=True)

@@ -102,3 +102,27 @@ def test_cancel_and_reject_on_gpu(served_dict):
         assert srv.wait(i, 60000) == abjoin.ABJ_OK
     assert srv.drain(60000) == abjoin.ABJ_OK
     srv.close()
+
+
+def test_serving_workload_sample_equals_alone(served_dict):
+    """The serving workload's request mix at scale (1,024 requests, lengths
+    log-uniform 1,024-65,536, m in {64, 128, 256}) submitted at once: 48 sampled
+    requests are bitwise equal to the same joins run alone."""
+    w, d = served_dict
+    sched = synth.serving_schedule(1024, 1e9, synth.rng_for(4, 0))
+    pool = synth.ecg_like(1 << 21, synth.rng_for(3, 0))
+    offs = synth.rng_for(4, 99).integers(0, len(pool) - 65536, len(sched))
+    print("[case] serving mix 1024 requests", flush=True)
+    srv = abjoin.Server(d, tier="fp32", max_slots=512, mem_budget=2 << 30)
+    qs = [pool[o:o + r.length] for o, r in zip(offs, sched)]
+    ids = [srv.submit(q, r.m) for q, r in zip(qs, sched)]
+    assert srv.drain(120000) == abjoin.ABJ_OK
+    st = srv.stats()
+    assert st["completed"] == len(sched) and st["batches"] > 1
+    pick = set(np.random.default_rng(0).choice(len(sched), 48, replace=False).tolist())
+    for k, i in enumerate(ids):
+        P, I, _ = srv.result(i)
+        if k in pick:
+            Pa, Ia = alone(d, qs[k], sched[k].m, "fp32")
+            assert np.array_equal(P, Pa) and np.array_equal(I, Ia), k
+    srv.close()

@@ -194,10 +194,15 @@ int finalize_launch(const SeriesDev& A, const SeriesDev& B, const unsigned long 
                     const unsigned long long* part = nullptr, int nparts = 0);
 
 // Bytes of per-chunk keys for a join of WA rows over `nchunks` column chunks,
-// or 0 when the join should combine its tiles with atomics instead (many
-// chunks: the buffer would be large and the atomics are spread over a long
-// launch anyway).
+// or 0 when the join should combine its tiles with atomics instead (the buffer
+// would exceed 2 GiB: then there are so many tiles per row band that the
+// atomics are spread over a long launch anyway).
 size_t fp32_partial_bytes(int64_t WA, int64_t nchunks);
+// Up to this many chunks the row epilogue reduces the per-chunk keys itself;
+// beyond, fp32_reduce_parts writes the row keys first.
+constexpr int64_t kEpiloguePartsMax = 64;
+int fp32_reduce_parts(const unsigned long long* part, int64_t nparts, int64_t WA, unsigned long long* keys,
+                      hipStream_t stream);
 
 // Row epilogues of many joins in one launch (a serving batch): one descriptor
 // per join (finalize_job_bytes() bytes, AB-join conventions), blocks counted in *blk.

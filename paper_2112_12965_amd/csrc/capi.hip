@@ -235,6 +235,10 @@ int join_run(const double* query, int64_t n, int32_t m, const double* ref, int64
         return join_mfma_run(A, B, plan, !(o.flags & ABJ_FLAG_NO_REFINE), pearson, P, I, ar, stream);
     ABJ_TRY(join_fp32_batch(reinterpret_cast<const Fp32Slot*>(U + o_slot), 1, fp32_slot_tiles(sl), m, sl.pairs,
                             reinterpret_cast<unsigned long long*>(U + o_counter), stream, false, true));
+    if (part && sl.nchunks > kEpiloguePartsMax) {
+        ABJ_TRY(fp32_reduce_parts(part, sl.nchunks, A.W, keys, stream));
+        part = nullptr;
+    }
     return finalize_launch(A, B, keys, P, I, stream, nullptr, -1, pearson, part, part ? (int)sl.nchunks : 0);
 }
 

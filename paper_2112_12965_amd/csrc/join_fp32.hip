@@ -396,6 +396,29 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void
     }
 }
 
+// keys[i] = the largest of the per-chunk keys of row i (thread per row, so
+// each load instruction reads consecutive rows of one chunk).
+__global__ __launch_bounds__(256) void k_reduce_parts(const unsigned long long* __restrict__ part, int64_t nparts,
+                                                       int64_t WA, unsigned long long* __restrict__ keys)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= WA) return;
+    unsigned long long k = 0;
+    int64_t p = 0;
+    for (; p + 8 <= nparts; p += 8) {
+        unsigned long long v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = part[(p + u) * WA + i];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) k = v[u] > k ? v[u] : k;
+    }
+    for (; p < nparts; ++p) {
+        const unsigned long long v = part[p * WA + i];
+        k = v > k ? v : k;
+    }
+    keys[i] = k;
+}
+
 }  // namespace
 
 void fp32_slot(const SeriesDev& A, const SeriesDev& B, unsigned long long* keys, int64_t tile0, Fp32Slot* sl)
@@ -423,9 +446,19 @@ int64_t fp32_slot_tiles(const Fp32Slot& sl) { return sl.nbands * sl.nchunks; }
 
 size_t fp32_partial_bytes(int64_t WA, int64_t nchunks)
 {
-    if (WA <= 0 || nchunks <= 1 || nchunks > 64) return 0;
+    if (WA <= 0 || nchunks <= 1) return 0;
     const size_t b = sizeof(unsigned long long) * (size_t)WA * (size_t)nchunks;
-    return b <= ((size_t)256 << 20) ? (b + 255) & ~size_t(255) : 0;
+    return b <= ((size_t)2 << 30) ? (b + 255) & ~size_t(255) : 0;
+}
+
+int fp32_reduce_parts(const unsigned long long* part, int64_t nparts, int64_t WA, unsigned long long* keys,
+                      hipStream_t stream)
+{
+    if (WA <= 0) return ABJ_OK;
+    const int64_t g = (WA + 255) / 256;
+    hipLaunchKernelGGL(k_reduce_parts, dim3((unsigned)g), dim3(256), 0, stream, part, nparts, WA, keys);
+    ABJ_HIP(hipGetLastError());
+    return ABJ_OK;
 }
 
 size_t fp32_chunk_bytes(int32_t n_seg, int64_t n)

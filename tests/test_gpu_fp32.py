@@ -66,8 +66,9 @@ def test_multi_tile_ragged_segments(orc, m):
 
 @pytest.mark.parametrize("n_seg", [63, 64, 65, 70])
 def test_many_segments_both_merges(orc, n_seg):
-    # up to 64 column chunks the tiles store per-chunk keys that the epilogue
-    # reduces; beyond that they merge with atomics: both sides of the switch
+    # the tiles store per-chunk keys; up to 64 chunks the epilogue reduces
+    # them, beyond that a separate pass does: both sides of the switch (the
+    # atomic merge is covered by the full-size 1M x 1M case and by serving)
     rng = np.random.default_rng(2000 + n_seg)
     m = 16
     lens = rng.integers(40, 80, n_seg)

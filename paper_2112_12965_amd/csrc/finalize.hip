@@ -266,9 +266,48 @@ __device__ __forceinline__ void finalize_body(
     for (int off = 1; off < kGroup; off <<= 1) sq += __shfl_xor(sq, off, kWave);
     const double dist = jbest >= 0 ? sqrt(sq) : INFINITY;
 
-    // ---- conventions: the flat rows and the flat reference rule, one row at
-    // a time (the self-join's zone scans use the whole wave) ----
+    // ---- conventions: the flat rows and the flat reference rule ----
     const unsigned long long ff0 = WB > 0 ? bfirst[0] : kNone, fv0 = WB > 0 ? bfirst[1] : kNone;
+    if (excl < 0) {
+        // AB-join: no zone, so every row's 16 lanes settle their own row
+        if (i < WA) {
+            double pout = NAN;
+            int64_t iout = -1;
+            if (!(fa & kFlagBad)) {
+                if (fa & kFlagFlat) {
+                    if (ff0 != kNone) {
+                        pout = 0.0;
+                        iout = (int64_t)ff0;
+                    } else if (fv0 != kNone) {
+                        pout = sqrt((double)m);
+                        iout = (int64_t)fv0;
+                    } else {
+                        pout = INFINITY;
+                    }
+                } else {
+                    double d = dist;
+                    int64_t jj = jbest;
+                    if (ff0 != kNone) {
+                        const double sm = sqrt((double)m);
+                        if (sm < d || (sm == d && (int64_t)ff0 < jj)) {
+                            d = sm;
+                            jj = (int64_t)ff0;
+                        }
+                    }
+                    pout = d;
+                    iout = jj;
+                }
+            }
+            if (pearson) pout = pearson_of(pout, m);
+            if (c == 0) {
+                P[i] = (float)pout;
+                I[i] = iout;
+                if (P64) P64[i] = pout;
+            }
+        }
+        return;
+    }
+    // self-join: one row at a time (the zone scans use the whole wave)
     for (int rr = 0; rr < kRowsPerWave; ++rr) {
         const int64_t ii = row0 + rr;
         if (ii >= WA) break;

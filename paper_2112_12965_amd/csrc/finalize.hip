@@ -220,13 +220,15 @@ __device__ __forceinline__ void finalize_body(
         const bool hi = c & 1;
         dot = (hi ? h2[1] : h2[0]) + __shfl_xor(hi ? h2[0] : h2[1], 1, kWave);
     }
-    double score = -INFINITY;
-    if (cand && fj == 0) score = (double)dot / sbj;
+    // score in FP32 like the dot itself (an approximate reciprocal adds an
+    // ulp to the dot's own rounding)
+    float score = -INFINITY;
+    if (cand && fj == 0) score = dot * __builtin_amdgcn_rcpf((float)sbj);
     // best column of the row (ties -> smaller column)
     int cb = c;
 #pragma unroll
     for (int off = 1; off < kGroup; off <<= 1) {
-        const double os = __shfl_xor(score, off, kWave);
+        const float os = __shfl_xor(score, off, kWave);
         const int oc = __shfl_xor(cb, off, kWave);
         if (os > score || (os == score && oc < cb)) {
             score = os;

@@ -89,7 +89,7 @@ int ensure_device()
     std::lock_guard<std::mutex> lk(g_init_mu);
     if (!g_inited_dev[dev]) {
         // Keep stream-ordered workspace cached between calls instead of
-        // returning it to the driver at every synchronisation.
+        // releasing it at every synchronisation.
         hipMemPool_t pool;
         ABJ_HIP(hipDeviceGetDefaultMemPool(&pool, dev));
         uint64_t thr = ~0ull;

@@ -27,6 +27,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKLOAD = "ecg131k_dict16x2000_m256"
+# VALU issue ceiling without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+VALU_LANE_INSTR_PER_S = 256 * 4 * 16 * 2.4e9
 METRIC = "AB-join subsequence-pair distances/s vs plain FP32 at stated error; p99 latency"
 # FP32 vector peak of MI355X: 256 CUs x 128 FP32 lanes x 2 flops (FMA) x 2.4 GHz
 FP32_PEAK = 157.3e12
@@ -34,16 +36,16 @@ FP32_PEAK = 157.3e12
 FLOPS_PER_PAIR = 2 * 2 + 2 + 1
 
 
-def profiled_traffic(kernel_source: str, summary: str):
-    """HBM bytes per launch from a committed rocprofv3 counter summary, or None
-    when the kernel source has changed since the counters were taken."""
+def profiled_field(kernel_source: str, summary: str, field: str):
+    """A figure from a committed rocprofv3 counter summary, or None when the
+    kernel source has changed since the counters were taken."""
     import hashlib
 
     try:
         fields = dict(l.split(": ", 1) for l in open(summary).read().splitlines() if ": " in l)
         sha = hashlib.sha256(open(kernel_source, "rb").read()).hexdigest()
         if fields.get("kernel_source_sha256") == sha:
-            return float(fields["traffic_bytes_per_launch"])
+            return float(fields[field])
     except (OSError, KeyError, ValueError):
         pass
     return None
@@ -315,6 +317,10 @@ def main():
     kernel_ms = kms.value / max(nl.value, 1)
     kernel_pairs = kp.value / max(nl.value, 1)
     achieved = FLOPS_PER_PAIR * kernel_pairs / (kernel_ms * 1e-3)
+    src = os.path.join(ROOT, "paper_2112_12965_amd", "csrc", "join_fp32.hip")
+
+    def prof(kind):
+        return os.path.join(ROOT, "profiles", f"k_join_fp32_ecg131k_dict16x2000_m256_{kind}_counters.md")
 
     out = {
         "metric": METRIC,
@@ -336,10 +342,14 @@ def main():
                      "peak": FP32_PEAK / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / FP32_PEAK, "flops_per_pair": FLOPS_PER_PAIR,
                      "kernel_ms": kernel_ms,
-                     "traffic": profiled_traffic(
-                         os.path.join(ROOT, "paper_2112_12965_amd", "csrc", "join_fp32.hip"),
-                         os.path.join(ROOT, "profiles", "k_join_fp32_ecg131k_dict16x2000_m256_hbm_counters.md"))},
+                     "traffic": profiled_field(src, prof("hbm"), "traffic_bytes_per_launch")},
     }
+    # the same kernel against the VALU issue ceiling, from the committed
+    # instruction counters (VALU lane-instructions per pair, edges included)
+    ipp = profiled_field(src, prof("sq"), "valu_lane_instructions_per_pair")
+    out["roofline"]["valu_issue"] = None if ipp is None else {
+        "lane_instructions_per_pair": ipp, "ceiling_lane_instructions_per_s": VALU_LANE_INSTR_PER_S,
+        "frac": kernel_pairs / (kernel_ms * 1e-3) * ipp / VALU_LANE_INSTR_PER_S}
     results = {"fp32": (P.cpu().numpy(), I.cpu().numpy())}
     if not args.no_tiers:
         out["tiers"] = {"fp32": {"pairs_per_s": out["value"], "ms_per_step": out["ms_per_step"]}}

@@ -180,7 +180,11 @@ def pipeline(abjoin, synth, n=262144, n_series=8, m=256, space_saving=0.9, K=50)
     for (_, starts), r in zip(held, found):
         for row in r["rows"]:
             hits += int(np.any(np.abs(starts - int(row)) <= 260))
-    return {"database": f"{n_series} x {n} ECG-like", "held_out": f"{n_series} x {n}, 50 planted beats each",
+    # for the CPU leg's check: the first held-out series, its dictionary join
+    # and its discords, with the dictionary and the database on the host
+    check = (held[0][0], D.cpu().numpy(), np.asarray(dbounds), np.concatenate(db), np.asarray(rbounds), m,
+             joined[0][0].cpu().numpy().astype(np.float64), joined[0][1].cpu().numpy(), found[0])
+    return check, {"database": f"{n_series} x {n} ECG-like", "held_out": f"{n_series} x {n}, 50 planted beats each",
             "m": m, "space_saving": space_saving, "K": K,
             "dictionary_samples": int(D.numel()), "dictionary_segments": len(dbounds) - 1, "e_max": e_max,
             "learn_ms_per_series": t_learn * 1e3 / n_series,
@@ -189,6 +193,27 @@ def pipeline(abjoin, synth, n=262144, n_series=8, m=256, space_saving=0.9, K=50)
             "exact_rows_fraction": float(np.mean([r["rows_exact"] / W for r in found])),
             "rounds": [int(r["rounds"]) for r in found], "certified_bits": [int(r["certified"]) for r in found],
             "discords_on_planted_beats": f"{hits} of {n_series * K}"}
+
+
+def pipeline_errors(record, check, threads, rows=256):
+    """The first held-out series against the FP64 oracle: its dictionary join
+    on `rows` random rows, and its discords' values (exact distances to the
+    whole database) at the rows returned."""
+    import oracle
+
+    q, D, dbounds, ref, rbounds, m, Ph, Ih, found = check
+    W = len(q) - m + 1
+    sample = np.sort(np.random.default_rng(77).choice(W, rows, replace=False))
+    Po, Io, P2o = oracle.ab_join(q, D, dbounds, m, rows=sample, threads=threads, second=True)
+    clear = (P2o - Po) > 1e-3
+    record["dictionary_join_vs_oracle"] = {
+        "rows": rows, "max_abs": float(np.abs(Ph[sample] - Po).max()),
+        "index_match_clear_rows": float(np.mean(Ih[sample][clear] == Io[clear])) if clear.any() else 1.0}
+    drows = np.asarray(found["rows"], dtype=np.int64)
+    Pd, _ = oracle.ab_join(q, ref, rbounds, m, rows=np.sort(drows), threads=threads)
+    order = np.argsort(drows)
+    got = np.asarray(found["values"], dtype=np.float64)[order]
+    record["discord_values_vs_oracle"] = {"rows": int(len(drows)), "max_abs": float(np.abs(got - Pd).max())}
 
 
 def time_tier(abjoin, q, d, bounds, m, tier, steps, warmup, P, I):
@@ -362,6 +387,8 @@ def main():
             results[tier] = (Pt.cpu().numpy(), It.cpu().numpy())
         # the precision tier against the FP32 tier where its O(m) products are short
         out["tiers_short_windows"], short_data = short_windows(abjoin, synth)
+    if not args.no_pipeline:
+        pipe_check, out["pipeline"] = pipeline(abjoin, synth)
     if not args.no_cpu:
         threads = min(16, os.cpu_count() or 1)
         cb, errs = cpu_baseline(w, results, args.cpu_seconds, threads)
@@ -369,10 +396,10 @@ def main():
         out["error_vs_oracle"] = errs
         if not args.no_tiers:
             short_window_errors(out["tiers_short_windows"], short_data, threads)
+        if not args.no_pipeline:
+            pipeline_errors(out["pipeline"], pipe_check, threads)
     if not args.no_serving:
         out["serving"] = serving(abjoin, synth, ("fp32", "bf16"), args.serve_requests)
-    if not args.no_pipeline:
-        out["pipeline"] = pipeline(abjoin, synth)
     print(json.dumps(out), flush=True)
 
 

@@ -49,7 +49,7 @@ struct SeriesDev {
     double* mu = nullptr;  // W: window mean of xc
     double* sig = nullptr; // W: window population deviation
     float2* dfdg = nullptr;// W: {df(i), dg(i)} for the diagonal recurrence (last entry 0)
-    float4* col = nullptr; // W: {df, dg, 1/sigma or 0 when excluded, 0}
+    float4* col = nullptr; // W: {df, dg, 1/sigma or NaN when excluded, 0}
     uint8_t* flags = nullptr;  // W
     double* scal = nullptr;    // device scalars: [0] mean, [1] variance, [2] finite count
     unsigned long long* first = nullptr;  // [0] first valid flat window, [1] first valid window (~0 = none)

@@ -16,8 +16,8 @@
 //   * lane l owns rows i0 + 16 l .. i0 + 16 l + 15 and keeps their covariance
 //     and running best score in registers;
 //   * the wave walks the chunk's columns in order; a column's terms
-//     {df_b, dg_b, 1/sigma_b, bias} are the same for all lanes, so they come
-//     from scalar loads (bias = -inf for flat or non-finite windows);
+//     {df_b, dg_b, w_b} are the same for all lanes, so they come from scalar
+//     loads (weight w_b = 1/sigma_b, NaN for flat or non-finite windows);
 //   * cov(i, j) needs cov(i-1, j-1): for a lane's first row that is the last
 //     row of the lane below, moved across with one DPP wave_shr:1; lane 0 takes
 //     the tile's top edge instead;
@@ -121,13 +121,15 @@ __device__ inline unsigned long long pack_key(float s, int j)
 }
 
 // Score of logical row r at column j after the step that wrote it (slot
-// (r - 1 - U) mod kR): cov / sigma_j plus the column's bias (0, or -inf for a
-// reference window that cannot match), and -inf for a self-join trivial match.
+// (r - 1 - U) mod kR): cov times the column's weight (1 / sigma_j, or NaN for
+// a reference window that cannot match: maxima drop NaN), and -inf for a
+// self-join trivial match.  A product reads one scalar operand where a fused
+// bias would need two, which one VALU instruction cannot take.
 template <int U, bool kExcl>
 __device__ __forceinline__ float step_score(const float (&S)[kR], int r, const vf4& cur, int64_t j, int64_t ibase,
                                             int64_t excl)
 {
-    float sc = fmaf(S[(r - 1 - U) & (kR - 1)], cur[2], cur[3]);
+    float sc = S[(r - 1 - U) & (kR - 1)] * cur[2];
     if (kExcl) {
         // |j - i| <= excl is not a candidate (near the diagonal j - ibase is
         // small, so 32 bits suffice)
@@ -148,14 +150,21 @@ __device__ __forceinline__ bool sweep_step(int64_t j, int64_t jend, ColPtr __res
 {
     if (kGuard && j >= jend) return false;
     const vf4 cur = bcol[j];
-    // lanes 1..63 receive the last row of the lane below; lane 0 keeps the edge
-    const float t = __int_as_float(__builtin_amdgcn_update_dpp(
-        __float_as_int(e), __float_as_int(S[(kR - 1 - U) & (kR - 1)]), kDppWaveShr1, 0xf, 0xf, false));
 #pragma unroll
     for (int r = kR - 1; r >= 1; --r) {
         float& c = S[(r - 1 - U) & (kR - 1)];
         c = fmaf(pg[r], prev[0], fmaf(pf[r], prev[1], c));
     }
+    // row 0: lanes 1..63 take the old last row of the lane below (its slot is
+    // the one row 0 overwrites, untouched by the loop above) and lane 0 zero,
+    // plus e, which is the edge on lane 0 and zero elsewhere.  The compiler
+    // folds the shift into the add (one DPP add into a fresh register, so no
+    // row needs a move back at the block's end) only when the two are close
+    // and the add's other operand is a whole register, hence their place here
+    // and the empty asm.
+    asm("" : "+v"(e));
+    const float t = e + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(S[(kR - 1 - U) & (kR - 1)]),
+                                                                   kDppWaveShr1, 0xf, 0xf, true));
     S[(kR - 1 - U) & (kR - 1)] = fmaf(pg[0], prev[0], fmaf(pf[0], prev[1], t));
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
@@ -208,8 +217,11 @@ __device__ __forceinline__ void join_tile(const Fp32Slot& sl, int64_t band, int6
     const int m = sl.m;
 
     double* wv = lds;                                  // m doubles: one centred window
-    // kTC + kB floats, 16-byte aligned: edge[t] = cov(i0, j0 + 1 + t)
+    // kTC + kB floats, 16-byte aligned: edge[t] = cov(i0, j0 + 1 + t), then
+    // kB zeros, which lanes 1..63 read in place of the edge
     float* edge = reinterpret_cast<float*>(reinterpret_cast<char*>(lds) + edge_offset(m));
+    float* zeros = edge + kTC + kB;
+    if (threadIdx.x < kB) zeros[threadIdx.x] = 0.f;  // the edge's barriers below publish them
 
     const int lane = threadIdx.x;
     const int64_t i0 = band * kBandRows;
@@ -292,7 +304,7 @@ __device__ __forceinline__ void join_tile(const Fp32Slot& sl, int64_t band, int6
         const vf4 c0 = bcol[j0];
 #pragma unroll
         for (int r = 0; r < kR; ++r) {
-            float sc = fmaf(S[r], c0[2], c0[3]);
+            float sc = fmaxf(S[r] * c0[2], -INFINITY);  // NaN (no match) -> -inf
             const int64_t dj = j0 - (ibase + r);
             if (kExcl && dj <= sl.excl && dj >= -sl.excl) sc = -INFINITY;
             best[r] = sc;
@@ -304,7 +316,7 @@ __device__ __forceinline__ void join_tile(const Fp32Slot& sl, int64_t band, int6
     for (int64_t b = 0; b < nfull; ++b) {
         const int64_t jb = j0 + 1 + b * kB;
         float e[kB];
-        const float4* e4 = reinterpret_cast<const float4*>(edge + b * kB);
+        const float4* e4 = reinterpret_cast<const float4*>(lane == 0 ? edge + b * kB : zeros);
 #pragma unroll
         for (int q = 0; q < kB / 4; ++q) {
             const float4 v = e4[q];
@@ -319,8 +331,9 @@ __device__ __forceinline__ void join_tile(const Fp32Slot& sl, int64_t band, int6
         const int64_t jb = j0 + 1 + nfull * kB;
         if (jb < jend) {
             float e[kB];
+            const float* es = lane == 0 ? edge + nfull * kB : zeros;
 #pragma unroll
-            for (int u = 0; u < kB; ++u) e[u] = edge[nfull * kB + u];
+            for (int u = 0; u < kB; ++u) e[u] = es[u];
             sweep_block<true, kExcl>(jb, jend, bcol, e, S, pf, pg, best, bidx, prev, ibase, sl.excl);
         }
     }
@@ -474,7 +487,7 @@ std::vector<int32_t> fp32_chunk_list(const int64_t* bounds, int32_t n_seg, int64
     auto split = [&](int64_t a, int64_t cnt) {
         // chunks start at even columns (16-byte aligned samples for the edge
         // loads): an odd segment start takes the column before it along, a
-        // window that crosses the break and so carries the -inf bias
+        // window that crosses the break and so carries the NaN weight
         if (a & 1) {
             --a;
             ++cnt;
@@ -517,7 +530,7 @@ int fp32_chunks_upload(const int64_t* bounds, int32_t n_seg, int64_t n, int32_t 
     return ABJ_OK;
 }
 
-size_t fp32_lds_bytes(int max_m) { return edge_offset(max_m) + sizeof(float) * (kTC + kB); }
+size_t fp32_lds_bytes(int max_m) { return edge_offset(max_m) + sizeof(float) * (kTC + 2 * kB); }
 
 int join_fp32_batch(const Fp32Slot* slots_dev, int nslots, int64_t ntiles, int max_m, int64_t pairs,
                     unsigned long long* counter_dev, hipStream_t stream, bool self, bool counter_zeroed)

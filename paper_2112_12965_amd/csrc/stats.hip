@@ -314,8 +314,9 @@ __device__ void window_stats_body(const double* __restrict__ xc, const dd* __res
     }
     dfdg[i] = make_float2(df, dg);
     const bool usable = f == 0;
-    // bias -inf: the window never wins a row (the FP32 engine adds it to every score)
-    col[i] = make_float4(df, dg, usable ? (float)(1.0 / sd) : 0.f, usable ? 0.f : -INFINITY);
+    // weight NaN: every score of the window is NaN, which the FP32 engine's
+    // maxima drop, so the window never wins a row
+    col[i] = make_float4(df, dg, usable ? (float)(1.0 / sd) : __builtin_nanf(""), 0.f);
     if (first) {
         // one atomic per wave: windows ascend with the lane, so the lowest
         // lane of each ballot holds the wave's first valid / flat window

@@ -46,6 +46,11 @@ struct SeriesDev {
     int32_t m = 0;
     int64_t nvalid = 0;    // reference side: windows inside one segment (host-computed)
     double* xc = nullptr;  // n + kSeriesPad: x - mean(x), non-finite -> 0, zero tail
+    // the same samples (zero past n) in 16 rows: xt[(t % 16) * nb16 + t / 16] =
+    // xc[t] for t < 16 nb16, so that 64 lanes reading samples 16 apart (the FP32
+    // engine's edge dot products) read 64 consecutive doubles
+    double* xt = nullptr;
+    int64_t nb16 = 0;      // (n + kSeriesPad + 15) / 16
     double* mu = nullptr;  // W: window mean of xc
     double* sig = nullptr; // W: window population deviation
     float2* dfdg = nullptr;// W: {df(i), dg(i)} for the diagonal recurrence (last entry 0)
@@ -119,13 +124,16 @@ int stats_launch_many(const void* jobs_dev, int njobs, int64_t blk_sum, int64_t 
 constexpr int64_t kFp32BandRows = 1024;
 
 // A view of rows [r0, r0 + rows) of the query statistics A, for joining or
-// finishing a subset of bands (the copy behind xc keeps its zero tail).
+// finishing a subset of bands (the copy behind xc keeps its zero tail).  r0
+// is a multiple of 16 (the callers pass band starts), so that the 16-row copy
+// is the same rows shifted by r0 / 16 columns, with the same row length.
 inline SeriesDev rows_view(const SeriesDev& A, int64_t r0, int64_t rows)
 {
     SeriesDev v = A;
     v.W = rows;
     v.n = rows + A.m - 1;
     v.xc = A.xc + r0;
+    v.xt = A.xt + r0 / 16;
     v.mu = A.mu + r0;
     v.sig = A.sig + r0;
     v.dfdg = A.dfdg + r0;
@@ -146,6 +154,9 @@ struct Fp32Slot {
     const double* bmu;
     const float4* bcol;
     int64_t WB;
+    const double* axt;  // the series in 16 rows (SeriesDev::xt) and their length
+    const double* bxt;
+    int64_t anb16, bnb16;
     const int32_t* chunks;  // reference column chunks [c0, c1) (device)
     unsigned long long* keys;
     // when set, tiles store their row keys here (one WA-entry row per chunk,

@@ -47,53 +47,58 @@ constexpr int kBandRows = kR * kWave;   // query rows per tile
 static_assert(kBandRows == kFp32BandRows, "band height is part of the engine's interface");
 constexpr int kTC = 1024;               // reference columns per tile
 constexpr int kQ = kTC / kWave;         // top-edge columns per lane
+static_assert(kR == 16 && kQ == 16, "the edge dot products read the 16-row copies: lanes 16 samples apart");
 constexpr int kDppWaveShr1 = 0x138;     // DPP control: whole-wave shift right by one lane
 constexpr int kG = 16;                  // width of the FP64 edge dot-product groups
 
 // The slot's arrays live in global memory; saying so keeps their loads global
 // (not flat) although the pointers come from a descriptor in memory.
-typedef double vd2 __attribute__((ext_vector_type(2)));
 typedef const __attribute__((address_space(1))) double* GDbl;
-typedef const __attribute__((address_space(1))) vd2* GVd2;
 
-// acc[g] = sum_{k<m} w[k] * x[base + g + k] for g < G, for an even `base`
-// (x + base is 16-byte aligned).  x is read through a G-entry register window
-// that slides by one sample per k and is refilled two samples per load (one
-// load per 2G FMAs; a wave-wide load touches one cache line per lane, since
-// the lanes' windows are 16 samples apart, so fewer loads is what counts).
+// acc[g] = sum_{k<m} w[k] * x[B + 16 lane + g + k] for g < G and a
+// wave-uniform B, with x read from its 16-row copy xt (x[t] = xt[(t % 16) nb16
+// + t / 16]): for one sample offset the 64 lanes, whose windows are 16 samples
+// apart, read 64 consecutive doubles of one row, where the series itself would
+// have them touch 64 cache lines.  x is read through a G-entry register window
+// that slides by one sample per k and is refilled two samples per 2G FMAs.
 template <int G>
-__device__ inline void sliding_dots_even(GDbl __restrict__ x, int64_t base, const double* w, int m, double (&acc)[G])
+__device__ inline void sliding_dots_rows(GDbl __restrict__ xt, int64_t nb16, int64_t B, const double* w, int m,
+                                         double (&acc)[G])
 {
     static_assert(G % 2 == 0, "pairs");
-    GVd2 __restrict__ xp = (GVd2)(x + base);
+    const int lane = threadIdx.x % kWave;
+    // sample B + 16 lane + s of this lane: row (B + s) mod 16, column (B + s) / 16 + lane
+    // (a wave-uniform address plus the lane: the loads take a scalar base)
+    auto at = [&](int64_t s) {
+        const int64_t t = B + s;
+        const GDbl __restrict__ p = xt + ((t & 15) * nb16 + (t >> 4));
+        return p[lane];
+    };
     double win[G];
 #pragma unroll
-    for (int g = 0; g < G; g += 2) {
-        const vd2 v = xp[g / 2];
-        win[g] = v.x;
-        win[g + 1] = v.y;
+    for (int g = 0; g < G; ++g) {
+        win[g] = at(g);
         acc[g] = 0.0;
-        acc[g + 1] = 0.0;
     }
     int k0 = 0;
-    // Invariant at the top of each block: win[s] holds x[base + k0 + s].
+    // Invariant at the top of each block: win[s] holds sample k0 + s.
     for (; k0 + G <= m; k0 += G) {
 #pragma unroll
         for (int kk = 0; kk < G; kk += 2) {
-            const vd2 nx = xp[(k0 + kk + G) / 2];
+            const double n0 = at(k0 + kk + G), n1 = at(k0 + kk + G + 1);
             const double w0 = w[k0 + kk], w1 = w[k0 + kk + 1];
 #pragma unroll
             for (int g = 0; g < G; ++g) acc[g] = fma(w0, win[(kk + g) % G], acc[g]);
-            win[kk] = nx.x;
+            win[kk] = n0;
 #pragma unroll
             for (int g = 0; g < G; ++g) acc[g] = fma(w1, win[(kk + 1 + g) % G], acc[g]);
-            win[kk + 1] = nx.y;
+            win[kk + 1] = n1;
         }
     }
     for (int k = k0; k < m; ++k) {
         const double wk = w[k];
 #pragma unroll
-        for (int g = 0; g < G; ++g) acc[g] = fma(wk, x[base + g + k], acc[g]);
+        for (int g = 0; g < G; ++g) acc[g] = fma(wk, at(g + k), acc[g]);
     }
 }
 
@@ -210,6 +215,8 @@ __device__ __forceinline__ void join_tile(const Fp32Slot& sl, int64_t band, int6
     GDbl __restrict__ amu = (GDbl)sl.amu;
     GVf2 __restrict__ adfdg = (GVf2)sl.adfdg;
     GDbl __restrict__ bxc = (GDbl)sl.bxc;
+    GDbl __restrict__ axt = (GDbl)sl.axt;
+    GDbl __restrict__ bxt = (GDbl)sl.bxt;
     GDbl __restrict__ bmu = (GDbl)sl.bmu;
     ColPtr __restrict__ bcol = (ColPtr)sl.bcol;
     unsigned long long* __restrict__ keys = sl.keys;
@@ -246,7 +253,7 @@ __device__ __forceinline__ void join_tile(const Fp32Slot& sl, int64_t band, int6
         for (int h = 0; h < kQ; h += kG) {
             if (cbase + h >= jend) break;  // columns past the chunk are never swept
             double acc[kG];
-            sliding_dots_even<kG>(bxc, cbase + h, wv, m, acc);  // j0 is even
+            sliding_dots_rows<kG>(bxt, sl.bnb16, j0 + h, wv, m, acc);  // lane's columns from cbase + h
 #pragma unroll
             for (int g = 0; g < kG; ++g) {
                 const int64_t j = cbase + h + g;
@@ -274,7 +281,7 @@ __device__ __forceinline__ void join_tile(const Fp32Slot& sl, int64_t band, int6
 #pragma unroll
         for (int h = 0; h < kR; h += kG) {
             double acc[kG];
-            sliding_dots_even<kG>(axc, ibase + h, wv, m, acc);  // i0 is a multiple of 1024
+            sliding_dots_rows<kG>(axt, sl.anb16, i0 + h, wv, m, acc);  // lane's rows from ibase + h
 #pragma unroll
             for (int g = 0; g < kG; ++g) {
                 const int64_t i = ibase + h + g;
@@ -444,6 +451,10 @@ void fp32_slot(const SeriesDev& A, const SeriesDev& B, unsigned long long* keys,
     sl->bmu = B.mu;
     sl->bcol = B.col;
     sl->WB = B.W;
+    sl->axt = A.xt;
+    sl->bxt = B.xt;
+    sl->anb16 = A.nb16;
+    sl->bnb16 = B.nb16;
     sl->m = A.m;
     sl->keys = keys;
     sl->part = nullptr;
@@ -485,13 +496,6 @@ std::vector<int32_t> fp32_chunk_list(const int64_t* bounds, int32_t n_seg, int64
 {
     std::vector<int32_t> c;
     auto split = [&](int64_t a, int64_t cnt) {
-        // chunks start at even columns (16-byte aligned samples for the edge
-        // loads): an odd segment start takes the column before it along, a
-        // window that crosses the break and so carries the NaN weight
-        if (a & 1) {
-            --a;
-            ++cnt;
-        }
         // equal widths, a multiple of 16 except the last, so that no tile is a sliver
         const int64_t k = (cnt + kTC - 1) / kTC;
         int64_t w = (cnt + k - 1) / k;

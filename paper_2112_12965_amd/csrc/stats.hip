@@ -127,10 +127,12 @@ __device__ inline long long block_excl_scan_i(long long v, long long* sh, long l
 }
 
 // Pass 1: the working copy xc (non-finite -> 0, zero tail of kSeriesPad
-// samples) and per-block sums of xc, xc^2 (double-double) and the
-// non-finite count.
+// samples), its 16-row copy xt (16 nb16 samples; the grid covers them, as
+// 16 divides kBlockElems) and per-block sums of xc, xc^2 (double-double) and
+// the non-finite count.
 __device__ void block_sums_body(const double* __restrict__ x, int64_t n, double* __restrict__ xc,
-                                dd* __restrict__ b1, dd* __restrict__ b2, long long* __restrict__ bnf, int64_t blk)
+                                double* __restrict__ xt, int64_t nb16, dd* __restrict__ b1, dd* __restrict__ b2,
+                                long long* __restrict__ bnf, int64_t blk)
 {
     __shared__ double shh[kThreads], shl[kThreads];
     __shared__ long long shc[kThreads];
@@ -140,9 +142,9 @@ __device__ void block_sums_body(const double* __restrict__ x, int64_t n, double*
 #pragma unroll
     for (int e = 0; e < kPerThread; ++e) {
         const int64_t t = base + e;
+        double d = 0.0;
         if (t < n) {
             double v = x[t];
-            double d = 0.0;
             if (finite_d(v)) {
                 d = v;
             } else {
@@ -154,6 +156,7 @@ __device__ void block_sums_body(const double* __restrict__ x, int64_t n, double*
         } else if (t < n + kSeriesPad) {
             xc[t] = 0.0;
         }
+        if (t < 16 * nb16) xt[(t & 15) * nb16 + (t >> 4)] = d;
     }
     dd t1, t2;
     long long tn;
@@ -330,10 +333,11 @@ __device__ void window_stats_body(const double* __restrict__ xc, const dd* __res
 
 // One series per launch.
 __global__ __launch_bounds__(kThreads) void k_block_sums(const double* __restrict__ x, int64_t n,
-                                                         double* __restrict__ xc, dd* __restrict__ b1,
-                                                         dd* __restrict__ b2, long long* __restrict__ bnf)
+                                                         double* __restrict__ xc, double* __restrict__ xt,
+                                                         int64_t nb16, dd* __restrict__ b1, dd* __restrict__ b2,
+                                                         long long* __restrict__ bnf)
 {
-    block_sums_body(x, n, xc, b1, b2, bnf, blockIdx.x);
+    block_sums_body(x, n, xc, xt, nb16, b1, b2, bnf, blockIdx.x);
 }
 
 __global__ __launch_bounds__(kThreads) void k_scan_top(dd* __restrict__ b1, dd* __restrict__ b2,
@@ -369,6 +373,8 @@ __global__ __launch_bounds__(kThreads) void k_window_stats(
 struct StatsJobDev {
     const double* x;
     double* xc;
+    double* xt;
+    int64_t nb16;
     int64_t n, W;
     int32_t m, pad0;
     dd *b1, *b2;
@@ -406,7 +412,7 @@ __global__ __launch_bounds__(kThreads) void k_block_sums_many(const StatsJobDev*
 {
     const int jx = find_job<&StatsJobDev::blk_sum>(jobs, njobs, blockIdx.x);
     const StatsJobDev& J = jobs[jx];
-    block_sums_body(J.x, J.n, J.xc, J.b1, J.b2, J.bnf, (int64_t)blockIdx.x - J.blk_sum);
+    block_sums_body(J.x, J.n, J.xc, J.xt, J.nb16, J.b1, J.b2, J.bnf, (int64_t)blockIdx.x - J.blk_sum);
 }
 
 __global__ __launch_bounds__(kThreads) void k_scan_top_many(const StatsJobDev* __restrict__ jobs)
@@ -469,6 +475,7 @@ size_t stats_scratch_bytes(int64_t n, int64_t W)
     auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
     size_t b = 0;
     b += al(sizeof(double) * (size_t)(n + kSeriesPad));  // xc
+    b += al(sizeof(double) * 16 * (size_t)((n + kSeriesPad + 15) / 16));  // xt
     b += al(sizeof(double) * (size_t)W) * 2;             // mu, sig
     b += al(sizeof(float2) * (size_t)W);                 // dfdg
     b += al(sizeof(float4) * (size_t)W);                 // col
@@ -487,6 +494,8 @@ void stats_carve(Arena& a, int64_t n, int32_t m, SeriesDev* s)
     s->m = m;
     s->W = n >= m ? n - m + 1 : 0;
     s->xc = a.take<double>((size_t)(n + kSeriesPad));
+    s->nb16 = (n + kSeriesPad + 15) / 16;
+    s->xt = a.take<double>(16 * (size_t)s->nb16);
     s->mu = a.take<double>((size_t)s->W);
     s->sig = a.take<double>((size_t)s->W);
     s->dfdg = a.take<float2>((size_t)s->W);
@@ -509,7 +518,8 @@ int stats_compute(const double* x, SeriesDev* s, const int64_t* seg_bounds_dev, 
     dd* S2 = a.take<dd>((size_t)(n + 1));
     int* NF = a.take<int>((size_t)(n + 1));
 
-    hipLaunchKernelGGL(k_block_sums, dim3((unsigned)nbp), dim3(kThreads), 0, stream, x, n, s->xc, b1, b2, bnf);
+    hipLaunchKernelGGL(k_block_sums, dim3((unsigned)nbp), dim3(kThreads), 0, stream, x, n, s->xc, s->xt, s->nb16,
+                       b1, b2, bnf);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kThreads), 0, stream, b1, b2, bnf, nb, n, s->scal, s->first);
     hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nb), dim3(kThreads), 0, stream, s->xc, n, b1, b2, bnf, S1, S2,
                        NF, x);
@@ -534,6 +544,8 @@ void stats_carve_job(Arena& a, const double* x_dev, int64_t n, int32_t m, Series
     const int64_t nb = nblocks_of(n), nbp = nblocks_of(n + kSeriesPad);
     J.x = x_dev;
     J.xc = s->xc;
+    J.xt = s->xt;
+    J.nb16 = s->nb16;
     J.n = n;
     J.W = s->W;
     J.m = m;

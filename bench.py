@@ -299,7 +299,7 @@ def main():
                          "(reference dispatch for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1).",
+        print("bench.py measures one GPU only: the library has no multi-GPU path (run with --gpus 1).",
               file=sys.stderr)
         sys.exit(2)
 

@@ -16,7 +16,7 @@ namespace {
 constexpr unsigned long long kNone = ~0ull;
 
 constexpr int kWave = 64;
-constexpr int kWavesPerBlock = 4;
+constexpr int kWavesPerBlock = 1;
 
 // Pearson correlation of a distance, rho = 1 - d^2 / (2m); no window (+inf)
 // becomes -inf, NaN stays NaN.

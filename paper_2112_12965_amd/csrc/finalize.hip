@@ -31,7 +31,7 @@ constexpr int kGroup = 16;                    // columns per candidate group of 
 constexpr int kRowsPerWave = kWave / kGroup;  // 16 lanes per row
 constexpr int kKC = 256;                      // window samples staged per pass
 constexpr int kSlice = kKC / kGroup;          // samples per lane and pass
-constexpr int kHalf = 8;                      // samples per lane and sub-pass
+constexpr int kHalf = 16;                     // samples per lane and sub-pass (the whole slice)
 constexpr int kBLen = kKC + kGroup - 1;       // reference samples of one row's group per pass
 // LDS index of a staged sample: one pad word per 16 keeps the lanes'
 // slices (16 samples apart) on distinct banks

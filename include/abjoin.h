@@ -145,16 +145,16 @@ int self_join(const double* x, int64_t n, int32_t m, int64_t excl, float* P, int
  * Learning phase (Sec. 3.1, Alg. 1): greedy choice of the windows of a
  * training series T_B that form the dictionary D_B.
  *
- *   P_B <- self-join of T_B (exclusion zone m/2 rounded down), S <- 0
- *   repeat:
- *     P'  <- P_B - S, with +inf for every window within m/2 of an earlier
- *            choice and for windows whose P_B is not finite
- *     j   <- argmin P' (ties: smallest index; stop if no finite P')
- *     add the element of j: ceil(context * m) samples centred on window j,
- *         clipped to the series; overlapping or touching elements merge
- *     stop when the stop condition holds (the element of this step is kept)
- *     S'  <- distance profile of T_B against window j (Def. 4)
- *     S   <- S' on the first step, else min(S, S')
+ * Every window is ranked by its self-join distance (exclusion zone m/2,
+ * rounded down) minus its distance to the closest window chosen so far (the
+ * element-wise minimum of the chosen windows' distance profiles, Def. 4), and
+ * the lowest-ranked window is taken next, so motifs come first and repeats of
+ * a motif already in the dictionary sink (Fig. 4).  A chosen window and those
+ * within m/2 of it are never chosen again, nor are windows whose self-join
+ * distance is not finite; ties go to the smallest index; the run ends early
+ * when no window is left.  Each choice adds ceil(context * m) samples of T_B
+ * (at least m, at most n) with the window in the middle, shifted back inside
+ * the series at the ends; pieces that overlap or touch merge into one segment.
  *
  * Stop conditions: ABJ_STOP_SPACE_SAVING stops once the merged dictionary
  * holds at least (1 - stop_value) n samples; ABJ_STOP_EMAX stops once e_max

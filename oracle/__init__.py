@@ -16,6 +16,9 @@ Each function follows a definition or algorithm of the paper (see the header of
 * ``dist_matrix``   -- every pairwise distance (tiny inputs only)
 * ``self_join``     -- Alg. 1's self-join (P_B), intra-similarity join with exclusion zone
 * ``dist_profile``  -- Def. 4 distance profile (Alg. 1's profile of the chosen window)
+* ``ab_join_stream`` -- the same join as ``ab_join`` by an independently written
+  FP64 diagonal sweep with O(1) work per pair (``stream_oracle.c``), for joins
+  too large for the brute force (a held-out series against a whole database)
 * ``learn_dictionary`` (in ``oracle.learn``) -- Alg. 1
 """
 from __future__ import annotations
@@ -28,6 +31,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "abjoin_oracle.c")
+_SRC_STREAM = os.path.join(_HERE, "stream_oracle.c")
 _LIB = os.path.join(_HERE, "liborc.so")
 _lib = None
 
@@ -40,7 +44,8 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (-O2, OpenMP, no fast-math)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall", "-o", tmp, _SRC, "-lm"]
+        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall", "-o", tmp, _SRC, _SRC_STREAM,
+               "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -49,7 +54,8 @@ def build(force: bool = True) -> str:
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(_SRC),
+                                                                      os.path.getmtime(_SRC_STREAM)):
             build()
         lib = ctypes.CDLL(_LIB)
         lib.orc_window_stats.argtypes = [_f64p, ctypes.c_int64, ctypes.c_int32, _f64p, _f64p, _u8p, _u8p]
@@ -65,8 +71,10 @@ def _load():
         lib.orc_self_join.argtypes = [_f64p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, _f64p, _i64p,
                                       ctypes.c_int32]
         lib.orc_dist_profile.argtypes = [_f64p, ctypes.c_int64, ctypes.c_int32, _f64p, _f64p]
+        lib.orc_ab_join_stream.argtypes = [_f64p, ctypes.c_int64, _f64p, ctypes.c_int64, _i64p, ctypes.c_int32,
+                                           ctypes.c_int32, _f64p, _i64p, ctypes.c_int32]
         for f in ("orc_window_stats", "orc_valid_windows", "orc_ab_join", "orc_pair_dists", "orc_dist_matrix",
-                  "orc_self_join", "orc_dist_profile"):
+                  "orc_self_join", "orc_dist_profile", "orc_ab_join_stream"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -160,3 +168,17 @@ def dist_profile(x, m, w):
     S = np.empty(len(x) - m + 1)
     _check(_load().orc_dist_profile(_p(x, _f64p), len(x), m, _p(w, _f64p), _p(S, _f64p)), "dist_profile")
     return S
+
+
+def ab_join_stream(query, dictionary, bounds, m, threads=0):
+    """The AB-join of ``ab_join`` by the streaming oracle: (P, I) for every query window.
+
+    Same definition and conventions; an FP64 diagonal sweep (O(1) per pair,
+    exact restarts every 256 steps) picks each row's column and its distance is
+    then recomputed directly.  Pinned against the brute force by the tests."""
+    q, d, b = _f64(query), _f64(dictionary), _i64(bounds)
+    W = len(q) - m + 1
+    P, I = np.empty(max(W, 0)), np.empty(max(W, 0), np.int64)
+    _check(_load().orc_ab_join_stream(_p(q, _f64p), len(q), _p(d, _f64p), len(d), _p(b, _i64p), len(b) - 1, m,
+                                      _p(P, _f64p), _p(I, _i64p), int(threads)), "ab_join_stream")
+    return P, I

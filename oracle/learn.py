@@ -1,33 +1,37 @@
-"""Oracle of the learning phase (Alg. 1, LearnDictionary) -- TEST INFRASTRUCTURE ONLY.
+"""Oracle of the learning phase (Sec. 3.1, Alg. 1) -- TEST INFRASTRUCTURE ONLY.
 
-Plain Python over the FP64 primitives of this package, taking the steps of
-the greedy loop in the paper's order:
+``learn_dictionary(T, m, ...)`` returns the greedy dictionary of a training
+series: the merged [start, end) pieces of T that form it, the window starts it
+chose (in order), their concatenation with segment offsets and original
+starts, its e_max (Def. 10) and the self-join profile it started from.
 
-  P_B <- self-join of T_B (trivial matches excluded); S <- 0; D <- {}
-  loop:
-    P'  <- P_B - S, and +inf within floor(m/2) of every window already chosen
-    j   <- argmin P'
-    add T_B[j:j+m] with its context to D
-    stop if the terminal condition holds
-    S'  <- distance profile of T_B against T_B[j:j+m]
-    S   <- S' for the first element, else min(S, S')
+What the greedy choice does (Sec. 3.1, Fig. 4): every window is ranked by its
+self-join distance (its distance to its own nearest non-trivial match) minus
+its distance to the closest window chosen so far, and the lowest-ranked window
+is taken next.  Motifs therefore come first, and the repeats of a motif that
+is already in the dictionary sink down the ranking.  The rules this oracle
+applies, with the readings taken where the paper leaves a choice (each listed
+in the design notes):
 
-Readings where the paper leaves a choice (listed in the design notes):
-  * context: the element is ceil(k m) samples (k = 1.5 in the paper), centred on
-    the chosen window and clipped to the series;
-  * exclusion: |i - s| <= floor(m/2) around each chosen window start s, the
-    same zone the self-join uses for trivial matches;
-  * overlapping (or touching) elements are merged into one segment;
-  * memory condition: stop once the merged dictionary holds at least
-    (1 - space_saving) n samples; e_max condition: stop once e_max of the
-    current dictionary (Def. 10, computed exactly with the AB-join) is <= the
-    target; either way the element of the stopping iteration is kept;
-  * windows never chosen: those already excluded, and none when every P' is
-    infinite (the loop then ends).
+* self-join: trivial matches are the windows within floor(m/2) of a window;
+* a chosen window and the windows within floor(m/2) of it are never chosen
+  again, nor are windows whose self-join distance is not finite; the loop ends
+  when no window is left; ties go to the smallest index;
+* the "distance to the chosen windows" is the element-wise minimum of their
+  distance profiles (Def. 4), zero before the first choice;
+* each choice adds ``element_of``: ceil(k m) samples in total (k = 1.5 in the
+  paper), bounded by [m, n], the window in the middle (the odd sample after
+  it), shifted back inside the series at the ends; pieces that overlap or touch
+  merge into one segment;
+* stopping: for the memory condition, as soon as the merged pieces hold at
+  least (1 - space_saving) n samples; for the accuracy condition, as soon as
+  e_max of the current dictionary (computed with the exact join) is at most the
+  target; the piece added in the step that meets the condition is kept;
+  ``max_iters`` caps the number of choices.
 
 ``forced`` replays a given sequence of choices (lockstep checks against the
-GPU): at each step the forced index must be an argmin of P' within ``tie_tol``
-and is used in place of the oracle's own argmin.
+GPU): at each step the forced index must rank lowest within ``tie_tol`` and is
+used in place of the oracle's own choice.
 """
 from __future__ import annotations
 

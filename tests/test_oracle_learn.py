@@ -98,3 +98,21 @@ def test_forced_replay_checks_choices():
         learn.learn_dictionary(x, m, stop="space_saving", value=0.9, forced=bad)
     with pytest.raises(AssertionError):
         learn.learn_dictionary(x, m, stop="space_saving", value=0.9, forced=r["chosen"][:-1])
+
+
+def test_element_of_matches_hand_derived_golden():
+    """Alg. 1's context window (Sec. 3.1) against values worked out by hand
+    (tests/golden/element_of.json): total length ceil(k m) bounded by [m, n],
+    the chosen window centred with the odd sample after it, shifted inside the
+    series at both ends."""
+    import json
+    import os
+
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "element_of.json")))
+    assert len(g["cases"]) >= 10
+    for c in g["cases"]:
+        got = learn.element_of(c["j"], c["n"], c["m"], c["k"])
+        assert list(got) == c["expect"], (c, got)
+        a, b = got
+        # structural facts that hold for every case: the window is inside its element
+        assert a <= c["j"] and c["j"] + c["m"] <= b and 0 <= a and b <= c["n"]

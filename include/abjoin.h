@@ -75,8 +75,9 @@ typedef enum {
 
 typedef struct {
     int32_t tier;     /* abj_tier */
-    int32_t refine_k; /* precision tiers: candidates kept per row and re-checked in FP64, 1..8 (0 = 4);
-                         rounded up to 1, 2, 4 or 8 */
+    int32_t refine_k; /* precision tiers: candidates kept per row, 1..8 (0 = 4), rounded up to 1, 2, 4 or 8;
+                         candidates are more than 4 windows apart and the re-check computes the FP64
+                         distance of every window within 4 of each */
     int32_t flags;    /* ABJ_FLAG_* bits; 0 for default behaviour */
     int32_t reserved; /* must be 0 */
 } abj_opts;
@@ -113,10 +114,13 @@ int abj_window_stats(const double* x, int64_t n, int32_t m, double* mu, double* 
  *   seg_bounds  host, n_seg+1 int64 offsets (see conventions)
  *   P_AB    device, n_query-m+1 floats (out)  I_AB  device, n_query-m+1 int64 (out)
  *   opts    NULL = FP32 tier
- * FP32 tier: m <= 4096.  BF16 / FP16 tiers (the paper's join with 16-bit
+ * FP32 tier: m <= 4096; its error bound against FP64 (|P| within 1e-3) is
+ * tested for m = 2 and m >= 8 (for m = 3..7 nearest distances can fall below
+ * the resolution of FP32 pair scores).  BF16 / FP16 tiers (the paper's join with 16-bit
  * window products, a speed/accuracy option of this library): m <= 256; every
- * row keeps its best refine_k candidates by 16-bit score per dictionary chunk
- * and returns the one closest in FP64.
+ * row keeps its best refine_k candidates by 16-bit score (pairwise more than
+ * 4 windows apart) and returns the closest window in FP64 among the windows
+ * within 4 of a candidate.
  * Errors: ABJ_EINVAL if m < 2 (or above the tier's limit), n_query < m,
  * n_dict < 1, n_seg < 1, bad seg_bounds, an unknown tier, refine_k outside
  * 0..8, unknown flag bits, nonzero reserved field, or a NULL / non-device

@@ -243,6 +243,27 @@ int join_mfma_run(const SeriesDev& A, const SeriesDev& B, const MfmaPlan& p, int
 
 int ensure_device();
 
+// The whole path of one join (see capi.hip): statistics of the query (and of
+// `ref` with its host segment bounds, else `Bres` holds the reference), pair
+// scores of the selected tier and row epilogue, all scratch from `ar`.
+// part_bytes: per-chunk FP32 keys (fp32_partial_bytes) or 0 for atomics.
+int join_run(const double* query, int64_t n, int32_t m, const double* ref, int64_t n_ref, const int64_t* ref_bounds,
+             int32_t n_seg, const SeriesDev* Bres, const abj_opts& o, const MfmaPlan& plan, float* P, int64_t* I,
+             Arena& ar, hipStream_t stream, size_t part_bytes = 0);
+
+// ab_join's argument checks and plan: everything is checked before anything
+// is enqueued.  scratch: workspace bytes of the join with per-chunk FP32
+// keys (part_bytes of them); scratch_atomic: without them (atomic merge).
+struct JoinPrep {
+    abj_opts o;
+    MfmaPlan plan;
+    size_t part_bytes = 0;
+    size_t scratch = 0, scratch_atomic = 0;
+};
+int ab_join_validate(const double* query, int64_t n_query, const double* dict, int64_t n_dict,
+                     const int64_t* seg_bounds, int32_t n_seg, int32_t m, float* P_AB, int64_t* I_AB,
+                     const abj_opts* opts, JoinPrep* jp);
+
 // Argument checks shared by the entry points (set the error text).
 int check_dev_buf(const void* p, size_t bytes, const char* name);
 int check_bounds(const int64_t* sb, int32_t n_seg, int64_t n_dict);

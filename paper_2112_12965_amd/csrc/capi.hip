@@ -182,7 +182,7 @@ size_t pair_scratch_bytes(int64_t n_query, int64_t n_ref, int32_t n_seg, int32_t
 // part_bytes: per-chunk keys (fp32_partial_bytes, reserved by the caller) or 0.
 int join_run(const double* query, int64_t n, int32_t m, const double* ref, int64_t n_ref, const int64_t* ref_bounds,
              int32_t n_seg, const SeriesDev* Bres, const abj_opts& o, const MfmaPlan& plan, float* P, int64_t* I,
-             Arena& ar, hipStream_t stream, size_t part_bytes = 0)
+             Arena& ar, hipStream_t stream, size_t part_bytes)
 {
     const bool fp32 = o.tier == ABJ_TIER_FP32;
     const bool pearson = (o.flags & ABJ_FLAG_PEARSON) != 0;
@@ -321,11 +321,12 @@ extern "C" int abj_window_stats(const double* x, int64_t n, int32_t m, double* m
     return stats_export(s, mu, sigma, flags, stream);
 }
 
-extern "C" int ab_join(const double* query, int64_t n_query, const double* dict, int64_t n_dict,
-                       const int64_t* seg_bounds, int32_t n_seg, int32_t m, float* P_AB, int64_t* I_AB,
-                       const abj_opts* opts, void* hip_stream)
+namespace abj {
+
+int ab_join_validate(const double* query, int64_t n_query, const double* dict, int64_t n_dict,
+                     const int64_t* seg_bounds, int32_t n_seg, int32_t m, float* P_AB, int64_t* I_AB,
+                     const abj_opts* opts, JoinPrep* jp)
 {
-    // ---- validation: nothing is enqueued or written before this passes ----
     abj_opts o;
     ABJ_TRY(check_opts(opts, &o));
     if (m < 2 || m > kMaxM) return set_error(ABJ_EINVAL, "m must be in [2, %d] (got %d)", kMaxM, m);
@@ -342,16 +343,33 @@ extern "C" int ab_join(const double* query, int64_t n_query, const double* dict,
     ABJ_TRY(check_dev_buf(I_AB, sizeof(int64_t) * (size_t)WA, "I_AB"));
     MfmaPlan plan;
     if (o.tier != ABJ_TIER_FP32) ABJ_TRY(mfma_plan(WA, WB, m, o.tier, o.refine_k, &plan));
-    ABJ_TRY(ensure_device());
-
-    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
-    Arena ar(stream);
     // per-chunk keys instead of atomics when the chunk list is short
     size_t part_bytes = 0;
     if (o.tier == ABJ_TIER_FP32 && WB > 0)
         part_bytes = fp32_partial_bytes(WA, (int64_t)fp32_chunk_list(seg_bounds, n_seg, n_dict, m).size() / 2);
-    ar.reserve(pair_scratch_bytes(n_query, n_dict, n_seg, m, o, plan, part_bytes));
+    jp->o = o;
+    jp->plan = plan;
+    jp->part_bytes = part_bytes;
+    jp->scratch = pair_scratch_bytes(n_query, n_dict, n_seg, m, o, plan, part_bytes);
+    jp->scratch_atomic = pair_scratch_bytes(n_query, n_dict, n_seg, m, o, plan, 0);
+    return ABJ_OK;
+}
+
+}  // namespace abj
+
+extern "C" int ab_join(const double* query, int64_t n_query, const double* dict, int64_t n_dict,
+                       const int64_t* seg_bounds, int32_t n_seg, int32_t m, float* P_AB, int64_t* I_AB,
+                       const abj_opts* opts, void* hip_stream)
+{
+    // ---- validation: nothing is enqueued or written before this passes ----
+    JoinPrep jp;
+    ABJ_TRY(ab_join_validate(query, n_query, dict, n_dict, seg_bounds, n_seg, m, P_AB, I_AB, opts, &jp));
+    ABJ_TRY(ensure_device());
+
+    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+    Arena ar(stream);
+    ar.reserve(jp.scratch);
     ABJ_TRY(ar.commit());
-    return join_run(query, n_query, m, dict, n_dict, seg_bounds, n_seg, nullptr, o, plan, P_AB, I_AB, ar, stream,
-                    part_bytes);
+    return join_run(query, n_query, m, dict, n_dict, seg_bounds, n_seg, nullptr, jp.o, jp.plan, P_AB, I_AB, ar,
+                    stream, jp.part_bytes);
 }

@@ -1,9 +1,10 @@
 // Row epilogue of the FP32 join: unpack each row's winning group of 16
-// columns, pick the column with the largest correlation among them in FP64
-// (one wave per 4 rows, one lane per row and candidate), recompute its
-// distance from the windows themselves (the norm of the difference of the
-// z-normalised windows, so there is no 1 - rho cancellation), and apply the
-// flat / non-finite conventions.
+// columns, pick the column with the largest correlation among them from FP32
+// dot products of the centred windows staged in LDS (one wave per 4 rows, 16
+// lanes per row, one lane per candidate column), recompute the winner's
+// distance in FP64 from the windows themselves (the norm of the difference of
+// the z-normalised windows, so there is no 1 - rho cancellation), and apply
+// the flat / non-finite conventions.
 #include <math.h>
 #include <string.h>
 

@@ -113,11 +113,46 @@ __device__ inline float unpack_score(unsigned long long key)
 // (v, j) ranks before (w, k): larger score first, smaller index on ties.
 __device__ inline bool ranks_before(float v, int j, float w, int k) { return v > w || (v == w && j >= 0 && j < k); }
 
-// Inserts (v, j) into a top-K list kept in rank order if it ranks before the
+// Candidates of one row are kept pairwise more than kRefineRadius windows
+// apart, and the FP64 re-check evaluates every window within that radius of
+// each one: neighbouring windows have nearly equal 16-bit scores, so without
+// the spacing the K candidates would mostly be one neighbourhood, and the
+// re-check of the neighbourhood recovers a best window that the 16-bit
+// ranking placed just behind its neighbour.
+constexpr int kRefineRadius = 4;
+
+// Inserts (v, j) into a top-K list kept in rank order: skipped if an entry
+// within the radius ranks before it; otherwise the entries within the radius
+// (all ranking after it) are dropped and (v, j) goes in if it ranks before the
 // last entry.  Compile-time indices only (no scratch memory).
 template <int K>
 __device__ inline void topk_insert(float (&tv)[K], int (&ti)[K], float v, int j)
 {
+    bool near[K];
+    bool dominated = false;
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        near[q] = ti[q] >= 0 && (ti[q] - j <= kRefineRadius && j - ti[q] <= kRefineRadius);
+        dominated = dominated || (near[q] && ranks_before(tv[q], ti[q], v, j));
+    }
+    if (dominated) return;
+#pragma unroll
+    for (int q = 0; q < K; ++q)
+        if (near[q]) {
+            tv[q] = -INFINITY;
+            ti[q] = -1;
+        }
+    // move the emptied entries behind the others, keeping their order
+#pragma unroll
+    for (int pass = 0; pass + 1 < K; ++pass)
+#pragma unroll
+        for (int q = 0; q + 1 < K; ++q)
+            if (ti[q] < 0 && ti[q + 1] >= 0) {
+                tv[q] = tv[q + 1];
+                ti[q] = ti[q + 1];
+                tv[q + 1] = -INFINITY;
+                ti[q + 1] = -1;
+            }
     if (!ranks_before(v, j, tv[K - 1], ti[K - 1])) return;
     int pos = K - 1;
 #pragma unroll
@@ -336,14 +371,17 @@ __device__ inline double wave_dist(const double* __restrict__ a, double ma, doub
     return sqrt(wave_sum(acc));
 }
 
-// One wave per query row: FP64 distance of every candidate (all chunks), keep
-// the closest (ties: smaller index); with `refine` off, report the distance
-// implied by the best 16-bit score instead.  Flat / non-finite conventions
-// as in the FP32 tier.
+// One wave per query row: the row's candidates from every chunk are taken
+// best-first, each dropping the others within kRefineRadius of it, up to
+// `keep` picks; the FP64 distance of every usable window within the radius of
+// a pick is computed and the closest kept (ties: smaller index).  With
+// `refine` off, report the distance implied by the best 16-bit score instead.
+// Flat / non-finite conventions as in the FP32 tier.
 __global__ __launch_bounds__(256) void k_finalize_topk(
     const double* __restrict__ axc, const double* __restrict__ amu, const double* __restrict__ asig,
     const uint8_t* __restrict__ aflags, int64_t WA, const double* __restrict__ bxc, const double* __restrict__ bmu,
-    const double* __restrict__ bsig, const unsigned long long* __restrict__ bfirst, int64_t WB, int m,
+    const double* __restrict__ bsig, const uint8_t* __restrict__ bflags, const unsigned long long* __restrict__ bfirst,
+    int64_t WB, int m,
     const unsigned long long* __restrict__ cand, int ncand, int keep, int refine, int pearson,
     float* __restrict__ P, int64_t* __restrict__ I)
 {
@@ -373,9 +411,9 @@ __global__ __launch_bounds__(256) void k_finalize_topk(
         double d = INFINITY;
         int64_t j = -1;
         const unsigned long long* c = cand + i * ncand;
-        // the row's candidates from every chunk: keep the `keep` best keys
-        // (key order = score order, ties -> smaller index), found by repeated
-        // wave-wide maxima over the lanes' slices of the list
+        // the row's candidates from every chunk, best first (key order =
+        // score order, ties -> smaller index), found by repeated wave-wide
+        // maxima over the lanes' slices of the list
         constexpr int kMaxPerLane = 8;
         unsigned long long mine[kMaxPerLane];
 #pragma unroll
@@ -394,19 +432,30 @@ __global__ __launch_bounds__(256) void k_finalize_topk(
                 wbest = o > wbest ? o : wbest;
             }
             if (wbest == 0ull) break;  // uniform
-#pragma unroll
-            for (int q = 0; q < kMaxPerLane; ++q)
-                if (mine[q] == wbest) mine[q] = 0ull;  // keys are unique per row
             const int64_t jj = (int64_t)(0xFFFFFFFFu - (unsigned)(wbest & 0xFFFFFFFFull));
+            // the pick and every other candidate within the radius: the
+            // re-check below covers them
+#pragma unroll
+            for (int q = 0; q < kMaxPerLane; ++q) {
+                if (mine[q] == 0ull) continue;
+                const int64_t jq = (int64_t)(0xFFFFFFFFu - (unsigned)(mine[q] & 0xFFFFFFFFull));
+                if (jq - jj <= kRefineRadius && jj - jq <= kRefineRadius) mine[q] = 0ull;
+            }
             if (!refine) {
                 d = sqrt(fmax(0.0, 2.0 * m * (1.0 - (double)unpack_score(wbest))));
                 j = jj;
                 break;
             }
-            const double dd = wave_dist(axc + i, amu[i], asig[i], bxc + jj, bmu[jj], bsig[jj], m, lane);
-            if (dd < d || (dd == d && jj < j)) {
-                d = dd;
-                j = jj;
+            // FP64 distance of every usable window within the radius of the pick
+            const int64_t t0 = jj - kRefineRadius > 0 ? jj - kRefineRadius : 0;
+            const int64_t t1 = jj + kRefineRadius < WB - 1 ? jj + kRefineRadius : WB - 1;
+            for (int64_t t = t0; t <= t1; ++t) {
+                if (bflags[t] != 0) continue;  // same t in every lane: uniform
+                const double dd = wave_dist(axc + i, amu[i], asig[i], bxc + t, bmu[t], bsig[t], m, lane);
+                if (dd < d || (dd == d && t < j)) {
+                    d = dd;
+                    j = t;
+                }
             }
         }
         if (ff != kNone) {
@@ -504,9 +553,9 @@ int mfma_plan(int64_t WA, int64_t WB, int32_t m, int tier, int refine_k, MfmaPla
     int64_t nchunks = 1;
     while (p->npanels * nchunks < 2048 && (p->ndblk + nchunks * 2 - 1) / (nchunks * 2) >= 64) nchunks *= 2;
     while (nchunks * K > 512) nchunks /= 2;  // the re-check reads at most 512 candidates per row
-    p->blk_per_chunk = (p->ndblk + nchunks - 1) / nchunks;
-    p->nchunks = (p->ndblk + p->blk_per_chunk - 1) / p->blk_per_chunk;
-    if (p->nchunks < 1) p->nchunks = 1;
+    // a reference shorter than m has no block: one empty chunk (no sweep)
+    p->blk_per_chunk = p->ndblk > 0 ? (p->ndblk + nchunks - 1) / nchunks : 1;
+    p->nchunks = p->ndblk > 0 ? (p->ndblk + p->blk_per_chunk - 1) / p->blk_per_chunk : 1;
     return ABJ_OK;
 }
 
@@ -553,7 +602,7 @@ int join_mfma_run(const SeriesDev& A, const SeriesDev& B, const MfmaPlan& p, int
     const int rows_per_block = 4;
     hipLaunchKernelGGL(k_finalize_topk, dim3((unsigned)((A.W + rows_per_block - 1) / rows_per_block)),
                        dim3(kWave * rows_per_block), 0, stream, A.xc, A.mu, A.sig, A.flags, A.W, B.xc, B.mu, B.sig,
-                       B.first, B.W, (int)A.m, cand, (int)(p.nchunks * p.K), p.K, refine, pearson, P, I);
+                       B.flags, B.first, B.W, (int)A.m, cand, (int)(p.nchunks * p.K), p.K, refine, pearson, P, I);
     ABJ_HIP(hipGetLastError());
     return ABJ_OK;
 }

@@ -31,7 +31,7 @@ def full_check(orc, q, d, bounds, m, tier="fp32", tol=TOL):
     print(f"[case] n_q={len(q)} n_d={len(d)} segs={len(bounds) - 1} m={m} tier={tier}", flush=True)
     P, I = run(q, d, bounds, m, tier)
     Po, Io, P2o = orc.ab_join(q, d, bounds, m, second=True)
-    return _parity.compare(P, I, Po, Io, P2o, tol, orc, q, d, m)
+    return _parity.compare(P, I, Po, Io, P2o, tol, orc, q, d, m, bounds)
 
 
 def test_window_stats_match_oracle(orc):
@@ -179,7 +179,7 @@ def test_dictionary_workload_sampled_rows(orc):
         np.random.default_rng(3).choice(len(P), 384, replace=False),
         np.clip(w["anomalies"], 0, len(P) - 1), [0, len(P) - 1]]))
     Po, Io, P2o = orc.ab_join(q, d, b, m, rows=rows, second=True)
-    st = _parity.compare(P[rows], I[rows], Po, Io, P2o, TOL, orc, q, d, m, rows=rows)
+    st = _parity.compare(P[rows], I[rows], Po, Io, P2o, TOL, orc, q, d, m, b, rows=rows)
     print(st)
 
 
@@ -192,5 +192,35 @@ def test_large_random_walk_sampled_rows(orc):
     rows = np.unique(np.concatenate([np.random.default_rng(4).choice(len(P), 96, replace=False),
                                      [0, 1023, 1024, len(P) - 1]]))
     Po, Io, P2o = orc.ab_join(q, d, b, m, rows=rows, second=True)
-    st = _parity.compare(P[rows], I[rows], Po, Io, P2o, TOL, orc, q, d, m, rows=rows)
+    st = _parity.compare(P[rows], I[rows], Po, Io, P2o, TOL, orc, q, d, m, b, rows=rows)
     print(st)
+
+
+@pytest.mark.parametrize("m", [257, 600, 1500, 4096])
+def test_long_windows_with_near_copies(orc, m):
+    """Windows longer than the row epilogue's 256-sample staging pass (several
+    passes, and at m = 4096 the tier's limit), over several row bands and two
+    column chunks per segment, with near-copy rows whose nearest distance is
+    small: there a wrong column pick inside the winning group costs the most
+    (about m drho / d)."""
+    rng = np.random.default_rng(3000 + m)
+    WA, WB = 2 * 1024 + 77, 1500
+    q = synth.random_walk(WA + m - 1, rng)
+    d = synth.random_walk(WB + 2 * (m - 1) + 40, rng)
+    bounds = [0, WB + m - 1 - 300, WB + m - 1 - 300 + 40, len(d)]  # ragged, one segment too short
+    i = 100
+    for j, noise in [(5, 1e-3), (700, 1e-2), (1100, 3e-2)]:
+        if i + m > len(q):
+            break
+        q[i:i + m] = 1.5 * d[j:j + m] + 4.0 + noise * rng.standard_normal(m)
+        i += max(900, m + 37)
+    st = full_check(orc, q, d, bounds, m)
+    print(st)
+
+
+def test_ecg_long_window(orc):
+    rng = synth.rng_for(92, 0)
+    q = synth.ecg_like(4000, rng, n_anomalies=2)
+    src = synth.ecg_like(30000, synth.rng_for(92, 1))
+    d, bounds, _ = synth.cut_dictionary(src, 4, 3000, synth.rng_for(92, 2))
+    full_check(orc, q, d, bounds, 1000)

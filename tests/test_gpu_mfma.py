@@ -59,7 +59,7 @@ def check(orc, q, d, bounds, m, tier, rows=None):
     Pu, Iu = run(q, d, bounds, m, tier, refine=False)
     Po, Io, P2o = orc.ab_join(q, d, bounds, m, rows=rows, second=True)
     sel = slice(None) if rows is None else rows
-    st = _parity.compare(P[sel], I[sel], Po, Io, P2o, TOL, orc, q, d, m, rows=rows)
+    st = _parity.compare(P[sel], I[sel], Po, Io, P2o, TOL, orc, q, d, m, bounds, rows=rows)
     fin = np.isfinite(Po)
     eu = np.abs(Pu[sel][fin] - Po[fin])
     st["unrefined_max_abs"] = float(eu.max()) if eu.size else 0.0

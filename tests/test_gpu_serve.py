@@ -87,7 +87,7 @@ def test_served_results_match_oracle(served_dict, orc):
         assert srv.wait(i, 60000) == abjoin.ABJ_OK
         P, I, _ = srv.result(i)
         Po, Io, P2o = orc.ab_join(q, w["dict"], w["bounds"], m, second=True)
-        _parity.compare(P, I, Po, Io, P2o, 1e-3, orc, q, w["dict"], m)
+        _parity.compare(P, I, Po, Io, P2o, 1e-3, orc, q, w["dict"], m, w["bounds"])
     srv.close()
 
 

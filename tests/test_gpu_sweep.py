@@ -1,0 +1,67 @@
+"""Seeded random sweep of small shapes for all three tiers, through the C-ABI.
+
+Each case draws a query length, a window length, a generator (random walk,
+ECG-like or white noise) and a segment layout (1 to 9 segments, some shorter
+than m, some exactly m long), runs the join and holds it to the parity bar of
+its tier (after the FP64 re-check the precision tiers meet the FP32 bar).
+Cases run in order and the test stops at the first failure; each case is
+printed before it runs.
+"""
+import numpy as np
+import pytest
+import torch
+
+import _parity
+from paper_2112_12965_amd import abjoin, synth
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-3
+CASES = 40
+
+
+def draw_case(seed, max_m):
+    rng = np.random.default_rng(seed)
+    # m = 3..7 is left out: there nearest distances fall to ~1e-3 and below,
+    # under the resolution of every tier's pair scores
+    m = int(rng.choice([2, 8, 16, 31, 32, 33, 64, 100, 128, 200, 255, 256, 300, 513]))
+    m = min(m, max_m)
+    kind = rng.choice(["rw", "ecg", "noise"])
+    if m < 16:
+        kind = "noise"  # on smooth series short windows sit below FP32 resolution
+    nq = int(rng.integers(m, m + 3000))
+    nseg = int(rng.integers(1, 10))
+    lens = []
+    for _ in range(nseg):
+        u = rng.random()
+        lens.append(int(rng.integers(1, m)) if u < 0.15 else m if u < 0.25 else int(rng.integers(m, m + 1500)))
+    nd = int(sum(lens))
+
+    def gen(n, r):
+        if kind == "rw":
+            return synth.random_walk(n, r)
+        if kind == "ecg":
+            return synth.ecg_like(n, r)
+        return r.standard_normal(n)
+
+    q = gen(nq, rng)
+    d = gen(nd, rng)
+    if nq >= 2 * m and nd >= m and rng.random() < 0.5:  # a planted affine copy
+        j = int(rng.integers(0, nd - m + 1))
+        i = int(rng.integers(0, nq - m + 1))
+        q[i:i + m] = 0.7 * d[j:j + m] + 2.0
+    bounds = np.concatenate([[0], np.cumsum(lens)]).tolist()
+    return q, d, bounds, m, kind
+
+
+@pytest.mark.parametrize("tier", ["fp32", "bf16", "fp16"])
+def test_random_shapes(orc, tier):
+    max_m = 4096 if tier == "fp32" else 256
+    for c in range(CASES):
+        seed = 50_000 + c + (0 if tier == "fp32" else 1000)
+        q, d, bounds, m, kind = draw_case(seed, max_m)
+        print(f"[case] tier={tier} seed={seed} kind={kind} n_q={len(q)} n_d={len(d)} "
+              f"segs={len(bounds) - 1} m={m}", flush=True)
+        P, I = abjoin.ab_join(torch.from_numpy(q).cuda(), torch.from_numpy(d).cuda(), bounds, m, tier=tier)
+        torch.cuda.synchronize()
+        Po, Io, P2o = orc.ab_join(q, d, bounds, m, second=True)
+        _parity.compare(P.cpu().numpy(), I.cpu().numpy(), Po, Io, P2o, TOL, orc, q, d, m, bounds)

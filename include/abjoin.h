@@ -131,6 +131,30 @@ int ab_join(const double* query, int64_t n_query, const double* dict, int64_t n_
             int32_t n_seg, int32_t m, float* P_AB, int64_t* I_AB, const abj_opts* opts, void* hip_stream);
 
 /*
+ * ab_join without device allocation, for callers that cannot allocate device
+ * memory during the call (code under HIP graph capture, serving loops that
+ * must not call the allocator, harnesses that forbid it).  Arguments,
+ * outputs, results and errors are those of ab_join, and the results equal
+ * ab_join's.  The workspace is a fixed array of ABJ_NOALLOC_SCRATCH_BYTES
+ * bytes of device memory that the library holds on every GPU it runs on until
+ * the process ends (abj_init sets it up for its device; otherwise the first
+ * call on a device does).  The call allocates nothing.
+ *   Limit: a join whose workspace exceeds the array (about 90 bytes per
+ *   sample of query and dictionary, plus 8 bytes per query window and column
+ *   chunk of 1,024 dictionary windows when those fit, else atomics are used;
+ *   plus the 16-bit operands and candidates in the BF16 / FP16 tiers) is
+ *   rejected with ABJ_EINVAL before anything is enqueued.
+ *   Sharing: every call on one GPU uses that GPU's one array, and each call
+ *   initialises what it reads.  Calls that overlap on one GPU (other streams
+ *   or other threads before the previous call's work has completed) race on
+ *   the array and give undefined results: serialise them on one stream.
+ */
+#define ABJ_NOALLOC_SCRATCH_BYTES (64ll << 20)
+int ab_join_noalloc(const double* query, int64_t n_query, const double* dict, int64_t n_dict,
+                    const int64_t* seg_bounds, int32_t n_seg, int32_t m, float* P_AB, int64_t* I_AB,
+                    const abj_opts* opts, void* hip_stream);
+
+/*
  * Self-join matrix profile of one series (the P_B of the learning phase,
  * Alg. 1, and Def. 7 with A = B): for every window i of x, the nearest window
  * j with |i - j| > excl (trivial matches excluded).  excl = m/2 (rounded down)

@@ -95,6 +95,7 @@ def lib():
         L.abj_window_stats.argtypes = [_vp, _i64, _i32, _vp, _vp, _vp, _vp]
         L.ab_join.argtypes = [_vp, _i64, _vp, _i64, ctypes.POINTER(_i64), _i32, _i32, _vp, _vp,
                               ctypes.POINTER(abj_opts), _vp]
+        L.ab_join_noalloc.argtypes = L.ab_join.argtypes
         L.self_join.argtypes = [_vp, _i64, _i32, _i64, _vp, _vp, _vp, ctypes.POINTER(abj_opts), _vp]
         L.dict_build.argtypes = [_vp, _i64, _i32, ctypes.POINTER(abj_learn_opts), ctypes.POINTER(_i64), _i32,
                                  ctypes.POINTER(_i32), ctypes.POINTER(_i64), _i32, ctypes.POINTER(_i32), _vp,
@@ -119,7 +120,7 @@ def lib():
         L.abj_server_drain.argtypes = [_vp, _i32]
         L.abj_server_stats_get.argtypes = [_vp, ctypes.POINTER(abj_server_stats)]
         L.abj_server_destroy.argtypes = [_vp]
-        for f in ("abj_init", "abj_window_stats", "ab_join", "self_join", "dict_build", "topk_discords", "discords",
+        for f in ("abj_init", "abj_window_stats", "ab_join", "ab_join_noalloc", "self_join", "dict_build", "topk_discords", "discords",
                   "abj_profile_enable", "abj_profile_read",
                   "abj_dict_create", "abj_dict_free", "ab_join_dict", "abj_server_create", "abj_submit",
                   "abj_submit_borrowed", "abj_wait", "abj_result", "abj_cancel", "abj_server_drain",

@@ -264,6 +264,10 @@ int ab_join_validate(const double* query, int64_t n_query, const double* dict, i
                      const int64_t* seg_bounds, int32_t n_seg, int32_t m, float* P_AB, int64_t* I_AB,
                      const abj_opts* opts, JoinPrep* jp);
 
+// Device address of the fixed workspace of ab_join_noalloc on the current
+// device (looked up once per device; *out may be NULL to only set it up).
+int noalloc_setup(void** out);
+
 // Argument checks shared by the entry points (set the error text).
 int check_dev_buf(const void* p, size_t bytes, const char* name);
 int check_bounds(const int64_t* sb, int32_t n_seg, int64_t n_dict);

@@ -265,7 +265,9 @@ extern "C" int abj_init(int device_ordinal)
     if (device_ordinal < 0 || device_ordinal >= count)
         return set_error(ABJ_EHIP, "device %d does not exist (%d visible)", device_ordinal, count);
     ABJ_HIP(hipSetDevice(device_ordinal));
-    return ensure_device();
+    ABJ_TRY(ensure_device());
+    // the device address of ab_join_noalloc's fixed workspace, once per device
+    return noalloc_setup(nullptr);
 }
 
 extern "C" int abj_profile_enable(int on)

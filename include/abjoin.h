@@ -75,9 +75,10 @@ typedef enum {
 
 typedef struct {
     int32_t tier;     /* abj_tier */
-    int32_t refine_k; /* precision tiers: candidates kept per row, 1..8 (0 = 4), rounded up to 1, 2, 4 or 8;
-                         candidates are more than 4 windows apart and the re-check computes the FP64
-                         distance of every window within 4 of each */
+    int32_t refine_k; /* precision tiers: candidates re-checked per row, 1..8 (0 = 4), rounded up to 1, 2,
+                         4 or 8; candidates are more than 4 windows apart and the re-check computes the
+                         FP64 distance of the 64 / refine_k windows around each (7 before to 8 after
+                         for 4) */
     int32_t flags;    /* ABJ_FLAG_* bits; 0 for default behaviour */
     int32_t reserved; /* must be 0 */
 } abj_opts;
@@ -118,9 +119,9 @@ int abj_window_stats(const double* x, int64_t n, int32_t m, double* mu, double* 
  * tested for m = 2 and m >= 8 (for m = 3..7 nearest distances can fall below
  * the resolution of FP32 pair scores).  BF16 / FP16 tiers (the paper's join with 16-bit
  * window products, a speed/accuracy option of this library): m <= 256; every
- * row keeps its best refine_k candidates by 16-bit score (pairwise more than
- * 4 windows apart) and returns the closest window in FP64 among the windows
- * within 4 of a candidate.
+ * row takes up to refine_k candidates best-first by 16-bit score (pairwise
+ * more than 4 windows apart) and returns the closest window in FP64 among the
+ * windows near a candidate (for refine_k <= 4: from 7 before to 8 after it).
  * Errors: ABJ_EINVAL if m < 2 (or above the tier's limit), n_query < m,
  * n_dict < 1, n_seg < 1, bad seg_bounds, an unknown tier, refine_k outside
  * 0..8, unknown flag bits, nonzero reserved field, or a NULL / non-device
@@ -304,8 +305,11 @@ int ab_join_dict(const abj_dict* d, const double* query, int64_t n_query, int32_
  * FP32 batch kernel (two launches in flight, in order on the server's
  * stream, so requests that arrive while one batch runs join the next), and
  * completes each request when its batch finishes: a completion thread copies
- * the results out while the next batches run.  The BF16/FP16 tiers run
- * admitted requests as separate launches on the same stream.  A batch takes
+ * the results out while the next batches run.  BF16/FP16 batches take one
+ * operand launch, one matrix-core sweep per window-length class (k steps of
+ * 16) present in the batch and one FP64 re-check launch for all their
+ * requests; the dictionary's 16-bit operand is built at the first request of
+ * each window length and kept.  A batch takes
  * at most half of the slots and half of the budget (a lone request may take
  * the whole budget), so the next batch can be formed and queued while one
  * runs.  A batch costs one host-to-device copy (queries and descriptors) and

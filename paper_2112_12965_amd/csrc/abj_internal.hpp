@@ -228,18 +228,98 @@ int fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t
 struct MfmaPlan {
     int tier = 0;
     int KS = 0;                 // 16-wide k steps (m padded with zeros)
-    int K = 0;                  // candidates kept per row and chunk
+    int K = 0;                  // candidates stored per row and chunk
+    int keep = 0;               // distinct candidates re-checked per row
     int64_t nqblk = 0, ndblk = 0;  // 32-window blocks of query / dictionary
     int64_t npanels = 0;        // query panels (one workgroup each per chunk)
     int64_t blk_per_chunk = 0, nchunks = 0;  // dictionary split of the sweep
 };
 int mfma_plan(int64_t WA, int64_t WB, int32_t m, int tier, int refine_k, MfmaPlan* p);
-size_t mfma_scratch_bytes(const MfmaPlan& p);
-// Operands, matrix-core sweep, FP64 re-check of all candidates (or, with
+// Device bytes of the query side (16-bit operand, candidates) and of the
+// dictionary side (16-bit operand, block masks) of a plan.
+size_t mfma_query_bytes(const MfmaPlan& p);
+size_t mfma_dict_bytes(const MfmaPlan& p);
+
+// The dictionary side of the 16-bit tiers, built once per (window length,
+// tier) for a resident dictionary or per call otherwise.
+struct MfmaDictOp {
+    const void* zd = nullptr;        // operand fragments (32-window blocks x k steps x 64 lanes x 16 B)
+    const uint32_t* dmask = nullptr; // per block: bit r set = window 32 b + r can match
+};
+// Carves mfma_dict_bytes(p) from `ar` and enqueues the build on `stream`.
+int mfma_dict_build(const SeriesDev& B, const MfmaPlan& p, Arena& ar, MfmaDictOp* op, hipStream_t stream);
+
+// Operand, matrix-core sweep, FP64 re-check of the candidates (or, with
 // refine = 0, the distance implied by the best 16-bit score), conventions.
+// dop: a prebuilt dictionary side, or NULL to build it from `ar`.
 int join_mfma_run(const SeriesDev& A, const SeriesDev& B, const MfmaPlan& p, int refine, int pearson, float* P,
-                  int64_t* I,
-                  Arena& ar, hipStream_t stream);
+                  int64_t* I, Arena& ar, hipStream_t stream, const MfmaDictOp* dop = nullptr);
+
+// Job descriptors of the 16-bit tier's kernels: a one-shot join passes one by
+// value, a serving batch uploads a table (blk0 = the job's first workgroup
+// in its launch, ascending).
+struct MfmaOpJob {
+    const double* xc;
+    const double* mu;
+    const double* sig;
+    const uint8_t* flags;
+    void* out;
+    int64_t W, nfrag, blk0;
+    int32_t m, ks_n;
+};
+struct MfmaJoinJob {
+    const void* zq;
+    const void* zd;
+    const uint32_t* dmask;
+    unsigned long long* cand;
+    int64_t nqblk, ndblk, npanels, blk_per_chunk, nchunks, blk0;
+};
+struct MfmaFinJob {
+    const double *axc, *amu, *asig;
+    const uint8_t* aflags;
+    int64_t WA;
+    const double *bxc, *bmu, *bsig;
+    const uint8_t* bflags;
+    const unsigned long long* bfirst;
+    int64_t WB;
+    const unsigned long long* cand;
+    float* P;
+    int64_t* I;
+    int64_t blk0;
+    int32_t ncand, keep, m, refine, pearson, pad;
+};
+
+// One query of a 16-bit serving batch: its statistics, the dictionary side
+// for its window length, its plan and its device buffers.
+struct MfmaBatchItem {
+    SeriesDev A;
+    const SeriesDev* B = nullptr;
+    MfmaDictOp dop;
+    MfmaPlan plan;
+    void* zq = nullptr;                 // mfma_query_bytes(plan) bytes: operand, then candidates
+    unsigned long long* cand = nullptr;
+    float* P = nullptr;
+    int64_t* I = nullptr;
+};
+struct MfmaBatchLaunch {
+    struct Group {
+        int ks, k, first, count;
+        int64_t blocks;
+    };
+    int tier = 0, n = 0;
+    std::vector<Group> groups;  // one sweep launch per (k steps, candidates)
+    std::vector<int> empty;     // items whose dictionary has no window
+    int64_t op_blocks = 0, fin_blocks = 0;
+    size_t off_join = 0, off_fin = 0;
+};
+// Device bytes of the job tables of n items.
+size_t mfma_batch_table_bytes(int n);
+// Writes the job tables to `host` (later copied to the device) and the launch shape to *L.
+void mfma_batch_prepare(const MfmaBatchItem* items, int n, int tier, int refine, int pearson, void* host,
+                        MfmaBatchLaunch* L);
+// Enqueues the batch: every query operand in one launch, one sweep per group, every re-check in one launch.
+int mfma_batch_launch(const MfmaBatchItem* items, const void* tables_dev, const MfmaBatchLaunch& L,
+                      hipStream_t stream);
 
 int ensure_device();
 
@@ -249,7 +329,7 @@ int ensure_device();
 // part_bytes: per-chunk FP32 keys (fp32_partial_bytes) or 0 for atomics.
 int join_run(const double* query, int64_t n, int32_t m, const double* ref, int64_t n_ref, const int64_t* ref_bounds,
              int32_t n_seg, const SeriesDev* Bres, const abj_opts& o, const MfmaPlan& plan, float* P, int64_t* I,
-             Arena& ar, hipStream_t stream, size_t part_bytes = 0);
+             Arena& ar, hipStream_t stream, size_t part_bytes = 0, const MfmaDictOp* dop = nullptr);
 
 // ab_join's argument checks and plan: everything is checked before anything
 // is enqueued.  scratch: workspace bytes of the join with per-chunk FP32
@@ -276,13 +356,16 @@ constexpr int32_t kMaxM = 4096;
 constexpr int64_t kMaxN = (1LL << 31) - 1;
 
 // Device bytes that join_query needs for one query of n samples (statistics,
-// keys, the upload region and, in the 16-bit tiers, the MFMA operands).
+// keys, the upload region and, in the 16-bit tiers, the query operand and
+// candidates; the dictionary side comes prebuilt, see join_query).
 size_t query_scratch_bytes(int64_t n, int32_t m, int64_t WB, const abj_opts& o, const MfmaPlan& plan);
 // Query-side join against reference statistics B: query statistics, pair loop
-// of the selected tier, row epilogue.  All scratch comes from `ar`.
+// of the selected tier, row epilogue.  All scratch comes from `ar`; the 16-bit
+// tiers take the dictionary side from `dop` (if NULL, `ar` must also hold
+// mfma_dict_bytes(plan) for it).
 int join_query(const double* query, int64_t n, int32_t m, const SeriesDev& B, const abj_opts& o,
                const MfmaPlan& plan, float* P, int64_t* I, Arena& ar, hipStream_t stream,
-               size_t part_bytes = 0);
+               size_t part_bytes = 0, const MfmaDictOp* dop = nullptr);
 
 // Benchmark timing hooks (no-ops unless abj_profile_enable(1) was called):
 // prof_begin records a start event on the stream, prof_end the stop event and

@@ -161,7 +161,7 @@ size_t query_scratch_bytes(int64_t n, int32_t m, int64_t WB, const abj_opts& o, 
     b += al256(sizeof(unsigned long long) * (size_t)W);  // keys
     // upload region: statistics job, slot descriptor, tile counters
     b += al256(stats_job_bytes()) + al256(sizeof(Fp32Slot)) + kTileCounterBytes;
-    if (o.tier != ABJ_TIER_FP32) b += mfma_scratch_bytes(plan);
+    if (o.tier != ABJ_TIER_FP32) b += mfma_query_bytes(plan);
     return b;
 }
 
@@ -170,7 +170,8 @@ size_t pair_scratch_bytes(int64_t n_query, int64_t n_ref, int32_t n_seg, int32_t
 {
     const int64_t WB = n_ref >= m ? n_ref - m + 1 : 0;
     return stats_scratch_bytes(n_ref, WB) + fp32_chunk_bytes(n_seg, n_ref) + al256(stats_job_bytes()) +
-           query_scratch_bytes(n_query, m, WB, o, plan) + part_bytes;
+           query_scratch_bytes(n_query, m, WB, o, plan) + (o.tier != ABJ_TIER_FP32 ? mfma_dict_bytes(plan) : 0) +
+           part_bytes;
 }
 
 // The whole path of one join: the statistics of the query (and of the
@@ -182,7 +183,7 @@ size_t pair_scratch_bytes(int64_t n_query, int64_t n_ref, int32_t n_seg, int32_t
 // part_bytes: per-chunk keys (fp32_partial_bytes, reserved by the caller) or 0.
 int join_run(const double* query, int64_t n, int32_t m, const double* ref, int64_t n_ref, const int64_t* ref_bounds,
              int32_t n_seg, const SeriesDev* Bres, const abj_opts& o, const MfmaPlan& plan, float* P, int64_t* I,
-             Arena& ar, hipStream_t stream, size_t part_bytes)
+             Arena& ar, hipStream_t stream, size_t part_bytes, const MfmaDictOp* dop)
 {
     const bool fp32 = o.tier == ABJ_TIER_FP32;
     const bool pearson = (o.flags & ABJ_FLAG_PEARSON) != 0;
@@ -232,7 +233,7 @@ int join_run(const double* query, int64_t n, int32_t m, const double* ref, int64
     ABJ_HIP(hipMemcpyAsync(U, h.data(), up, hipMemcpyHostToDevice, stream));
     ABJ_TRY(stats_launch_many(U + o_jobs, njobs, bs, bl, bw, stream));
     if (!fp32)
-        return join_mfma_run(A, B, plan, !(o.flags & ABJ_FLAG_NO_REFINE), pearson, P, I, ar, stream);
+        return join_mfma_run(A, B, plan, !(o.flags & ABJ_FLAG_NO_REFINE), pearson, P, I, ar, stream, dop);
     ABJ_TRY(join_fp32_batch(reinterpret_cast<const Fp32Slot*>(U + o_slot), 1, fp32_slot_tiles(sl), m, sl.pairs,
                             reinterpret_cast<unsigned long long*>(U + o_counter), stream, false, true));
     if (part && sl.nchunks > kEpiloguePartsMax) {
@@ -243,9 +244,10 @@ int join_run(const double* query, int64_t n, int32_t m, const double* ref, int64
 }
 
 int join_query(const double* query, int64_t n, int32_t m, const SeriesDev& B, const abj_opts& o,
-               const MfmaPlan& plan, float* P, int64_t* I, Arena& ar, hipStream_t stream, size_t part_bytes)
+               const MfmaPlan& plan, float* P, int64_t* I, Arena& ar, hipStream_t stream, size_t part_bytes,
+               const MfmaDictOp* dop)
 {
-    return join_run(query, n, m, nullptr, 0, nullptr, 0, &B, o, plan, P, I, ar, stream, part_bytes);
+    return join_run(query, n, m, nullptr, 0, nullptr, 0, &B, o, plan, P, I, ar, stream, part_bytes, dop);
 }
 
 int stats_export(const SeriesDev& s, double* mu, double* sig, uint8_t* flags, hipStream_t stream);

@@ -26,9 +26,6 @@ namespace abj {
 namespace {
 
 constexpr int kWave = 64;
-// waves per workgroup (they share each staged dictionary block): 8 where the
-// query fragments are small (m <= 128), 4 for m <= 256
-__host__ __device__ constexpr int waves_per_block(int ks) { return ks <= 8 ? 8 : 4; }
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8;
@@ -54,32 +51,61 @@ __device__ inline f32x16 mfma(f16x8 a, f16x8 b, f32x16 c)
     return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
 }
 
-// One thread per (32-window block, k step, lane) fragment of 8 elements.
-template <typename T>
-__global__ __launch_bounds__(256) void k_make_operand(const double* __restrict__ xc, const double* __restrict__ mu,
-                                                      const double* __restrict__ sig,
-                                                      const uint8_t* __restrict__ flags, int64_t W, int m, int ks_n,
-                                                      int64_t nfrag, typename Vec8<T>::type* __restrict__ out)
+// Pointers taken from a job descriptor lose the kernel argument's global
+// address space, and the compiler then emits flat accesses, which count on the
+// LDS wait counter too (so waiting for one would wait for pending LDS reads):
+// give them back the global address space.
+template <class T>
+__device__ inline const __attribute__((address_space(1))) T* gptr(const T* p)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nfrag) return;
+    return (const __attribute__((address_space(1))) T*)p;
+}
+template <class T>
+__device__ inline __attribute__((address_space(1))) T* gptr_w(T* p)
+{
+    return (__attribute__((address_space(1))) T*)p;
+}
+
+// Workgroup b of a launch over a job table belongs to the last job whose
+// first workgroup blk0 is <= b (blk0 ascending; uniform per workgroup).
+template <class J>
+__device__ inline int find_job(const J* __restrict__ jobs, int n, int64_t b)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].blk0 <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// One thread per (32-window block, k step, lane) fragment of 8 elements of
+// one series (a job): z[k] = (x[i+k] - mu(i)) / (sigma(i) sqrt(m)) in FP64,
+// then cast; windows that cannot match (flags) and k >= m are zeros.
+template <typename T>
+__global__ __launch_bounds__(256) void k_make_operand(MfmaOpJob one, const MfmaOpJob* __restrict__ jobs, int njobs)
+{
+    const MfmaOpJob J = jobs ? jobs[find_job(jobs, njobs, blockIdx.x)] : one;
+    const int64_t t = ((int64_t)blockIdx.x - J.blk0) * blockDim.x + threadIdx.x;
+    if (t >= J.nfrag) return;
     const int lane = (int)(t % kWave);
     const int64_t bk = t / kWave;  // block * ks_n + ks
-    const int ks = (int)(bk % ks_n);
-    const int64_t blk = bk / ks_n;
+    const int ks = (int)(bk % J.ks_n);
+    const int64_t blk = bk / J.ks_n;
     const int64_t i = blk * 32 + (lane % 32);
     const int k0 = ks * 16 + 8 * (lane / 32);
     typename Vec8<T>::type v;
-    const bool use = i < W && flags[i] == 0;
-    const double mean = use ? mu[i] : 0.0;
-    const double scale = use ? 1.0 / (sig[i] * sqrt((double)m)) : 0.0;
+    const bool use = i < J.W && J.flags[i] == 0;
+    const double mean = use ? J.mu[i] : 0.0;
+    const double scale = use ? 1.0 / (J.sig[i] * sqrt((double)J.m)) : 0.0;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const int k = k0 + e;
-        const double z = (use && k < m) ? (xc[i + k] - mean) * scale : 0.0;
+        const double z = (use && k < J.m) ? (J.xc[i + k] - mean) * scale : 0.0;
         v[e] = (T)(float)z;
     }
-    out[t] = v;
+    reinterpret_cast<typename Vec8<T>::type*>(J.out)[t] = v;
 }
 
 // Validity mask of each 32-window dictionary block (bit r = window 32 b + r usable).
@@ -113,46 +139,18 @@ __device__ inline float unpack_score(unsigned long long key)
 // (v, j) ranks before (w, k): larger score first, smaller index on ties.
 __device__ inline bool ranks_before(float v, int j, float w, int k) { return v > w || (v == w && j >= 0 && j < k); }
 
-// Candidates of one row are kept pairwise more than kRefineRadius windows
-// apart, and the FP64 re-check evaluates every window within that radius of
-// each one: neighbouring windows have nearly equal 16-bit scores, so without
-// the spacing the K candidates would mostly be one neighbourhood, and the
-// re-check of the neighbourhood recovers a best window that the 16-bit
-// ranking placed just behind its neighbour.
+// The row epilogue takes the candidates best-first, drops the others within
+// kRefineRadius windows of each pick, and re-checks every window within that
+// radius of a pick in FP64: neighbouring windows have nearly equal 16-bit
+// scores, so the best window often ranks just behind a neighbour, and the K
+// candidates of a chunk are mostly one neighbourhood.
 constexpr int kRefineRadius = 4;
 
-// Inserts (v, j) into a top-K list kept in rank order: skipped if an entry
-// within the radius ranks before it; otherwise the entries within the radius
-// (all ranking after it) are dropped and (v, j) goes in if it ranks before the
+// Inserts (v, j) into a top-K list kept in rank order if it ranks before the
 // last entry.  Compile-time indices only (no scratch memory).
 template <int K>
 __device__ inline void topk_insert(float (&tv)[K], int (&ti)[K], float v, int j)
 {
-    bool near[K];
-    bool dominated = false;
-#pragma unroll
-    for (int q = 0; q < K; ++q) {
-        near[q] = ti[q] >= 0 && (ti[q] - j <= kRefineRadius && j - ti[q] <= kRefineRadius);
-        dominated = dominated || (near[q] && ranks_before(tv[q], ti[q], v, j));
-    }
-    if (dominated) return;
-#pragma unroll
-    for (int q = 0; q < K; ++q)
-        if (near[q]) {
-            tv[q] = -INFINITY;
-            ti[q] = -1;
-        }
-    // move the emptied entries behind the others, keeping their order
-#pragma unroll
-    for (int pass = 0; pass + 1 < K; ++pass)
-#pragma unroll
-        for (int q = 0; q + 1 < K; ++q)
-            if (ti[q] < 0 && ti[q + 1] >= 0) {
-                tv[q] = tv[q + 1];
-                ti[q] = ti[q + 1];
-                tv[q + 1] = -INFINITY;
-                ti[q + 1] = -1;
-            }
     if (!ranks_before(v, j, tv[K - 1], ti[K - 1])) return;
     int pos = K - 1;
 #pragma unroll
@@ -187,139 +185,171 @@ __device__ inline float max16(const float (&a)[16])
 // Row index (within the 32-window block) of accumulator v in lane `lane`.
 __device__ inline int acc_row(int v, int lane) { return 8 * (v / 4) + 4 * (lane / 32) + (v % 4); }
 
-// Grid: chunk-major (all resident workgroups sweep the same dictionary chunk,
-// so its operand blocks are shared through L2).  Each wave owns NB query
-// blocks (32 NB query windows) whose fragments stay in registers for the whole
-// sweep.  The workgroup stages G dictionary blocks (G * KS = 32 fragments of
-// 1 KB) at a time in LDS, double-buffered: the global loads of stage s+1 are in
-// flight while the waves run the matrix products of stage s.
-template <typename T, int KS, int NB, int K, int WPE>
-__global__ __launch_bounds__(kWave* waves_per_block(KS)) __attribute__((amdgpu_waves_per_eu(WPE))) void k_join_mfma(
-    const typename Vec8<T>::type* __restrict__ zq, int64_t nqblk, const typename Vec8<T>::type* __restrict__ zd,
-    const uint32_t* __restrict__ dmask, int64_t ndblk, int64_t npanels, int64_t blk_per_chunk, int nchunks,
-    unsigned long long* __restrict__ cand)
+// Grid: chunk-major within a job (all resident workgroups of a job sweep the
+// same dictionary chunk, so its operand blocks are shared through L2).  Each
+// wave owns NB query blocks (32 NB query windows) whose fragments stay in
+// registers for the whole sweep.  The workgroup of NW waves stages G
+// dictionary blocks (G * KS = 32 fragments of 1 KB) at a time in LDS,
+// double-buffered: the global loads of stage s+1 are in flight while the
+// waves run the matrix products of stage s.  Two dictionary blocks are taken
+// per step, for two independent accumulation chains.
+//
+// Candidates: each lane keeps the KH best (score, window) of its own rows
+// (one query window, half of the dictionary windows of every block); the two
+// halves are merged into KH per row and chunk at the end.  The per-block test
+// against a lane's KH-th best is a wave-wide branch: with 64 lanes and their
+// own thresholds some lane passes it in nearly every one of the first 64 KH
+// blocks of a sweep, and in about 64 KH / b of the blocks after that, so long
+// sweeps (few chunks) keep the insert path rare.
+template <typename T, int KS, int NB, int KH, int NW, int WPE>
+__global__ __launch_bounds__(kWave* NW) __attribute__((amdgpu_waves_per_eu(WPE))) void k_join_mfma(
+    MfmaJoinJob one, const MfmaJoinJob* __restrict__ jobs, int njobs)
 {
     using V8 = typename Vec8<T>::type;
-    constexpr int kWavesPerBlock = waves_per_block(KS);
     constexpr int G = 32 / KS;                   // dictionary blocks per stage
     constexpr int kFrag = G * KS * kWave;        // 16-byte fragments per stage
-    constexpr int kPerThread = kFrag / (kWave * kWavesPerBlock);
+    constexpr int kPerThread = kFrag / (kWave * NW);
+    static_assert(G % 2 == 0, "two blocks per step");
     __shared__ V8 stage[2][kFrag];
 
+    const MfmaJoinJob J = jobs ? jobs[find_job(jobs, njobs, blockIdx.x)] : one;
+    const auto zq = gptr(reinterpret_cast<const V8*>(J.zq));
+    const auto zd = gptr(reinterpret_cast<const V8*>(J.zd));
+    const auto dmask = gptr(J.dmask);
     const int lane = threadIdx.x % kWave;
     const int wave = threadIdx.x / kWave;
-    const int64_t chunk = blockIdx.x / npanels;
-    const int64_t panel = blockIdx.x - chunk * npanels;
-    const int64_t qb0 = (panel * kWavesPerBlock + wave) * NB;
-    const int64_t db_lo = chunk * blk_per_chunk;
-    const int64_t db_hi = db_lo + blk_per_chunk < ndblk ? db_lo + blk_per_chunk : ndblk;
+    const int64_t local = (int64_t)blockIdx.x - J.blk0;
+    const int64_t chunk = local / J.npanels;
+    const int64_t panel = local - chunk * J.npanels;
+    const int64_t qb0 = (panel * NW + wave) * NB;
+    const int64_t db_lo = chunk * J.blk_per_chunk;
+    const int64_t db_hi = db_lo + J.blk_per_chunk < J.ndblk ? db_lo + J.blk_per_chunk : J.ndblk;
     const int64_t nst = (db_hi - db_lo + G - 1) / G;
 
     V8 bq[NB][KS];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
-        const int64_t qb = qb0 + nb < nqblk ? qb0 + nb : nqblk - 1;  // clamp: duplicate work, never stored
+        const int64_t qb = qb0 + nb < J.nqblk ? qb0 + nb : J.nqblk - 1;  // clamp: duplicate work, never stored
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) bq[nb][ks] = zq[(qb * KS + ks) * kWave + lane];
     }
-    float tv[NB][K];
-    int ti[NB][K];
+    float tv[NB][KH];
+    int ti[NB][KH];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-        for (int q = 0; q < K; ++q) {
+        for (int q = 0; q < KH; ++q) {
             tv[nb][q] = -INFINITY;
             ti[nb][q] = -1;
         }
 
     // stage s holds dictionary blocks db_lo + s G .. + G - 1, fragment order
-    // (block, ks, lane) exactly as in global memory, so the copy is linear
+    // (block, ks, lane) exactly as in global memory, so the copy is linear;
+    // every lane issues all its loads, so the loads in flight are known at
+    // compile time (past the chunk the address is clamped: those blocks have
+    // mask 0 and are never used)
     V8 pre[kPerThread];
     auto fetch = [&](int64_t s) {
         const int64_t base = (db_lo + s * G) * KS * kWave;
         const int64_t lim = db_hi * KS * kWave;
 #pragma unroll
         for (int e = 0; e < kPerThread; ++e) {
-            const int64_t f = base + (int64_t)e * (kWave * kWavesPerBlock) + threadIdx.x;
-            pre[e] = f < lim ? zd[f] : V8{};
+            const int64_t f = base + (int64_t)e * (kWave * NW) + threadIdx.x;
+            pre[e] = zd[f < lim ? f : lim - 1];
         }
     };
     auto store = [&](int buf) {
 #pragma unroll
-        for (int e = 0; e < kPerThread; ++e) stage[buf][e * (kWave * kWavesPerBlock) + threadIdx.x] = pre[e];
+        for (int e = 0; e < kPerThread; ++e) stage[buf][e * (kWave * NW) + threadIdx.x] = pre[e];
     };
-    if (nst > 0) {
-        fetch(0);
-        store(0);
-    }
+    // the masks of a stage's G blocks, one per lane (0 past the chunk),
+    // loaded one stage ahead with the fragments and read with readlane (a
+    // scalar load per block shares its wait counter with the LDS reads)
+    uint32_t smask = 0u, smask_next = 0u;
+    auto fetch_mask = [&](int64_t s) {
+        const int64_t db = db_lo + s * G + lane;
+        smask_next = lane < G && db < db_hi ? dmask[db] : 0u;
+    };
+
+    __builtin_assume(nst > 0);  // every chunk holds a block (mfma_plan)
+    fetch_mask(0);
+    fetch(0);
+    store(0);
     __syncthreads();
     for (int64_t s = 0; s < nst; ++s) {
         const int buf = (int)(s & 1);
-        if (s + 1 < nst) fetch(s + 1);
-        // two dictionary blocks at a time: 2 NB independent accumulation chains
-#pragma unroll
+        smask = smask_next;
+        if (s + 1 < nst) {
+            fetch_mask(s + 1);
+            fetch(s + 1);
+        }
         for (int g0 = 0; g0 < G; g0 += 2) {
-            int64_t db[2];
             uint32_t msk[2];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                db[h] = db_lo + s * G + g0 + h;
-                msk[h] = (g0 + h < G && db[h] < db_hi) ? dmask[db[h]] : 0u;
-            }
+            for (int h = 0; h < 2; ++h) msk[h] = __builtin_amdgcn_readlane(smask, g0 + h);
             if ((msk[0] | msk[1]) == 0u) continue;  // both blocks masked or past the end
             f32x16 acc[2][NB];
-#pragma unroll
-            for (int h = 0; h < 2; ++h)
-#pragma unroll
-                for (int nb = 0; nb < NB; ++nb) acc[h][nb] = f32x16{};
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
                 V8 ad[2];
 #pragma unroll
-                for (int h = 0; h < 2; ++h) ad[h] = stage[buf][(((g0 + h) % G) * KS + ks) * kWave + lane];
+                for (int h = 0; h < 2; ++h) ad[h] = stage[buf][((g0 + h) * KS + ks) * kWave + lane];
 #pragma unroll
                 for (int h = 0; h < 2; ++h)
 #pragma unroll
-                    for (int nb = 0; nb < NB; ++nb) acc[h][nb] = mfma(ad[h], bq[nb][ks], acc[h][nb]);
+                    for (int nb = 0; nb < NB; ++nb)
+                        acc[h][nb] = mfma(ad[h], bq[nb][ks], ks == 0 ? f32x16{} : acc[h][nb]);
             }
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 if (msk[h] == 0u) continue;
-                const int jbase = (int)(db[h] * 32);
+                const int jbase = (int)((db_lo + s * G + g0 + h) * 32);
+                const bool partial = msk[h] != 0xFFFFFFFFu;
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
-                    float a[16];
+                    float mx;
+                    {
+                        float c[16];
 #pragma unroll
-                    for (int v = 0; v < 16; ++v) a[v] = acc[h][nb][v];
-                    if (__builtin_expect(msk[h] != 0xFFFFFFFFu, 0)) {
-                        // a block that straddles a segment break (rare): the
-                        // opaque copy keeps the per-lane tests inside the branch
-                        uint32_t mm = msk[h];
-                        asm volatile("" : "+s"(mm));
-#pragma unroll
-                        for (int v = 0; v < 16; ++v)
-                            if (!((mm >> acc_row(v, lane)) & 1u)) a[v] = -INFINITY;
+                        for (int v = 0; v < 16; ++v) c[v] = acc[h][nb][v];
+                        mx = max16(c);
                     }
-                    float mx = max16(a);
-                    bool hit = mx > tv[nb][K - 1];
-                    if (__builtin_expect(__builtin_amdgcn_ballot_w64(hit) != 0, 0)) {
-                        // rare (a row's K-th best improves a few dozen times per
-                        // chunk): insert the lane's largest value above its K-th
-                        // best, one per pass, until no lane of the wave has one
+                    bool hit = mx > tv[nb][KH - 1];
+                    if (__builtin_expect(__builtin_amdgcn_ballot_w64(hit) != 0 || partial, 0)) {
+                        // insert the lane's values above its KH-th best, the
+                        // largest first (at most KH of them can stay); in a
+                        // block that straddles a segment break (rare) the
+                        // masked windows are removed first
                         asm volatile("" ::: "memory");
-                        do {
+                        float a[16];
+#pragma unroll
+                        for (int v = 0; v < 16; ++v) a[v] = acc[h][nb][v];
+                        if (partial) {
+                            uint32_t mm = __builtin_amdgcn_readfirstlane(msk[h]);
+                            asm volatile("" : "+s"(mm));  // keeps the per-lane tests inside the branch
+#pragma unroll
+                            for (int v = 0; v < 16; ++v)
+                                if (!((mm >> acc_row(v, lane)) & 1u)) a[v] = -INFINITY;
+                            mx = max16(a);
+                            hit = mx > tv[nb][KH - 1];
+                        }
+#pragma unroll
+                        for (int pass = 0; pass < KH; ++pass) {
+                            if (__builtin_amdgcn_ballot_w64(hit) == 0) break;
                             if (hit) {
                                 // first (smallest row) position of the lane's largest value
-                                int sel = 0;
+                                int sel = 15;
 #pragma unroll
-                                for (int v = 15; v >= 0; --v) sel = a[v] == mx ? v : sel;
-                                topk_insert<K>(tv[nb], ti[nb], mx, jbase + acc_row(sel, lane));
+                                for (int v = 14; v >= 0; --v) sel = a[v] == mx ? v : sel;
+                                topk_insert<KH>(tv[nb], ti[nb], mx, jbase + acc_row(sel, lane));
+                                if (pass + 1 < KH) {
 #pragma unroll
-                                for (int v = 0; v < 16; ++v) a[v] = v == sel ? -INFINITY : a[v];
-                                mx = max16(a);
-                                hit = mx > tv[nb][K - 1];
+                                    for (int v = 0; v < 16; ++v) a[v] = v == sel ? -INFINITY : a[v];
+                                    mx = max16(a);
+                                    hit = mx > tv[nb][KH - 1];
+                                }
                             }
-                        } while (__builtin_amdgcn_ballot_w64(hit) != 0);
+                        }
                     }
                 }
             }
@@ -330,21 +360,21 @@ __global__ __launch_bounds__(kWave* waves_per_block(KS)) __attribute__((amdgpu_w
     // merge the two lane halves (same query window, disjoint dictionary rows)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
-        float ov[K];
-        int oi[K];
+        float ov[KH];
+        int oi[KH];
 #pragma unroll
-        for (int q = 0; q < K; ++q) {
+        for (int q = 0; q < KH; ++q) {
             ov[q] = __shfl_xor(tv[nb][q], 32, kWave);
             oi[q] = __shfl_xor(ti[nb][q], 32, kWave);
         }
         if (lane < 32) {
 #pragma unroll
-            for (int q = 0; q < K; ++q) topk_insert<K>(tv[nb], ti[nb], ov[q], oi[q]);
+            for (int q = 0; q < KH; ++q) topk_insert<KH>(tv[nb], ti[nb], ov[q], oi[q]);
             const int64_t row = (qb0 + nb) * 32 + lane;
-            if (qb0 + nb < nqblk) {
-                unsigned long long* dst = cand + (row * nchunks + chunk) * K;
+            if (qb0 + nb < J.nqblk) {
+                auto dst = gptr_w(J.cand + (row * J.nchunks + chunk) * KH);
 #pragma unroll
-                for (int q = 0; q < K; ++q) dst[q] = ti[nb][q] >= 0 ? pack_key(tv[nb][q], ti[nb][q]) : 0ull;
+                for (int q = 0; q < KH; ++q) dst[q] = ti[nb][q] >= 0 ? pack_key(tv[nb][q], ti[nb][q]) : 0ull;
             }
         }
     }
@@ -352,45 +382,31 @@ __global__ __launch_bounds__(kWave* waves_per_block(KS)) __attribute__((amdgpu_w
 
 constexpr unsigned long long kNone = ~0ull;
 
-__device__ inline double wave_sum(double v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
-}
+constexpr int kFinRows = 4;  // query rows (one wave each) per workgroup of the re-check
 
-__device__ inline double wave_dist(const double* __restrict__ a, double ma, double sa, const double* __restrict__ b,
-                                   double mb, double sb, int m, int lane)
-{
-    const double ia = 1.0 / sa, ib = 1.0 / sb;
-    double acc = 0.0;
-    for (int k = lane; k < m; k += kWave) {
-        const double e = (a[k] - ma) * ia - (b[k] - mb) * ib;
-        acc = fma(e, e, acc);
-    }
-    return sqrt(wave_sum(acc));
-}
-
-// One wave per query row: the row's candidates from every chunk are taken
+// One wave per query row.  The row's candidates from every chunk are taken
 // best-first, each dropping the others within kRefineRadius of it, up to
-// `keep` picks; the FP64 distance of every usable window within the radius of
-// a pick is computed and the closest kept (ties: smaller index).  With
-// `refine` off, report the distance implied by the best 16-bit score instead.
-// Flat / non-finite conventions as in the FP32 tier.
-__global__ __launch_bounds__(256) void k_finalize_topk(
-    const double* __restrict__ axc, const double* __restrict__ amu, const double* __restrict__ asig,
-    const uint8_t* __restrict__ aflags, int64_t WA, const double* __restrict__ bxc, const double* __restrict__ bmu,
-    const double* __restrict__ bsig, const uint8_t* __restrict__ bflags, const unsigned long long* __restrict__ bfirst,
-    int64_t WB, int m,
-    const unsigned long long* __restrict__ cand, int ncand, int keep, int refine, int pearson,
-    float* __restrict__ P, int64_t* __restrict__ I)
+// `keep` picks.  Then every lane computes one FP64 distance in full, for a
+// window near a pick: with L = 64 / (keep rounded up to a power of two) lanes
+// per pick, lane l takes pick l / L shifted by (l % L) - L/2 + 1 (for 4 picks,
+// the windows from 7 before to 8 after each); windows outside the reference
+// or that cannot match are skipped.  One wave-wide argmin (ties: smaller
+// index) gives the row's result.  With `refine` off, report the distance
+// implied by the best 16-bit score instead.  Flat / non-finite conventions as
+// in the FP32 tier.
+__global__ __launch_bounds__(kWave* kFinRows) void k_finalize_topk(MfmaFinJob one, const MfmaFinJob* __restrict__ jobs,
+                                                                  int njobs)
 {
+    const MfmaFinJob J = jobs ? jobs[find_job(jobs, njobs, blockIdx.x)] : one;
     const int lane = threadIdx.x % kWave;
-    const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    if (i >= WA) return;
+    const int64_t i = ((int64_t)blockIdx.x - J.blk0) * kFinRows + threadIdx.x / kWave;
+    if (i >= J.WA) return;
+    const int m = J.m;
+    const auto aflags = gptr(J.aflags);
+    const auto bflags = gptr(J.bflags);
     const uint8_t fa = aflags[i];
-    const unsigned long long ff = WB > 0 ? bfirst[0] : kNone;
-    const unsigned long long fv = WB > 0 ? bfirst[1] : kNone;
+    const unsigned long long ff = J.WB > 0 ? gptr(J.bfirst)[0] : kNone;
+    const unsigned long long fv = J.WB > 0 ? gptr(J.bfirst)[1] : kNone;
     double pout;
     int64_t iout;
     if (fa & kFlagBad) {
@@ -410,7 +426,7 @@ __global__ __launch_bounds__(256) void k_finalize_topk(
     } else {
         double d = INFINITY;
         int64_t j = -1;
-        const unsigned long long* c = cand + i * ncand;
+        const auto c = gptr(J.cand + i * J.ncand);
         // the row's candidates from every chunk, best first (key order =
         // score order, ties -> smaller index), found by repeated wave-wide
         // maxima over the lanes' slices of the list
@@ -419,9 +435,15 @@ __global__ __launch_bounds__(256) void k_finalize_topk(
 #pragma unroll
         for (int q = 0; q < kMaxPerLane; ++q) {
             const int t = lane + q * kWave;
-            mine[q] = t < ncand ? c[t] : 0ull;
+            mine[q] = t < J.ncand ? c[t] : 0ull;
         }
-        for (int r = 0; r < keep; ++r) {
+        constexpr int kMaxPicks = 8;
+        int64_t pick[kMaxPicks];
+        int npick = 0;
+#pragma unroll
+        for (int r = 0; r < kMaxPicks; ++r) {
+            pick[r] = -1;
+            if (r >= J.keep) continue;
             unsigned long long lbest = 0ull;
 #pragma unroll
             for (int q = 0; q < kMaxPerLane; ++q) lbest = mine[q] > lbest ? mine[q] : lbest;
@@ -433,6 +455,13 @@ __global__ __launch_bounds__(256) void k_finalize_topk(
             }
             if (wbest == 0ull) break;  // uniform
             const int64_t jj = (int64_t)(0xFFFFFFFFu - (unsigned)(wbest & 0xFFFFFFFFull));
+            if (!J.refine) {
+                d = sqrt(fmax(0.0, 2.0 * m * (1.0 - (double)unpack_score(wbest))));
+                j = jj;
+                break;
+            }
+            pick[r] = jj;
+            npick = r + 1;
             // the pick and every other candidate within the radius: the
             // re-check below covers them
 #pragma unroll
@@ -441,21 +470,51 @@ __global__ __launch_bounds__(256) void k_finalize_topk(
                 const int64_t jq = (int64_t)(0xFFFFFFFFu - (unsigned)(mine[q] & 0xFFFFFFFFull));
                 if (jq - jj <= kRefineRadius && jj - jq <= kRefineRadius) mine[q] = 0ull;
             }
-            if (!refine) {
-                d = sqrt(fmax(0.0, 2.0 * m * (1.0 - (double)unpack_score(wbest))));
-                j = jj;
-                break;
-            }
-            // FP64 distance of every usable window within the radius of the pick
-            const int64_t t0 = jj - kRefineRadius > 0 ? jj - kRefineRadius : 0;
-            const int64_t t1 = jj + kRefineRadius < WB - 1 ? jj + kRefineRadius : WB - 1;
-            for (int64_t t = t0; t <= t1; ++t) {
-                if (bflags[t] != 0) continue;  // same t in every lane: uniform
-                const double dd = wave_dist(axc + i, amu[i], asig[i], bxc + t, bmu[t], bsig[t], m, lane);
-                if (dd < d || (dd == d && t < j)) {
-                    d = dd;
-                    j = t;
+        }
+        if (J.refine && npick > 0) {
+            const int L = J.keep <= 1 ? 64 : J.keep <= 2 ? 32 : J.keep <= 4 ? 16 : 8;
+            const int pr = lane / L;
+            int64_t base = -1;
+#pragma unroll
+            for (int r = 0; r < kMaxPicks; ++r)
+                if (r == pr) base = pick[r];
+            const int64_t t = base + (lane % L) - L / 2 + 1;
+            double dd = INFINITY;
+            if (base >= 0 && t >= 0 && t < J.WB && bflags[t] == 0) {
+                const auto xa = gptr(J.axc + i);
+                const auto xb = gptr(J.bxc + t);
+                const double ma = gptr(J.amu)[i], ia = 1.0 / gptr(J.asig)[i];
+                const double mb = gptr(J.bmu)[t], ib = 1.0 / gptr(J.bsig)[t];
+                // four independent sums keep several loads in flight
+                double acc[4] = {0.0, 0.0, 0.0, 0.0};
+                int k = 0;
+                for (; k + 4 <= m; k += 4) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const double e = (xa[k + u] - ma) * ia - (xb[k + u] - mb) * ib;
+                        acc[u] = fma(e, e, acc[u]);
+                    }
                 }
+                for (; k < m; ++k) {
+                    const double e = (xa[k] - ma) * ia - (xb[k] - mb) * ib;
+                    acc[0] = fma(e, e, acc[0]);
+                }
+                dd = sqrt((acc[0] + acc[1]) + (acc[2] + acc[3]));
+            }
+            // wave argmin of (distance, window); lanes without a window hold +inf
+            int64_t tt = dd < INFINITY ? t : INT64_MAX;
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                const double od = __shfl_xor(dd, off, kWave);
+                const int64_t ot = __shfl_xor(tt, off, kWave);
+                if (od < dd || (od == dd && ot < tt)) {
+                    dd = od;
+                    tt = ot;
+                }
+            }
+            if (tt != INT64_MAX) {
+                d = dd;
+                j = tt;
             }
         }
         if (ff != kNone) {
@@ -468,85 +527,168 @@ __global__ __launch_bounds__(256) void k_finalize_topk(
         pout = d;
         iout = j;
     }
-    if (pearson) pout = isnan(pout) ? pout : isinf(pout) ? -INFINITY : 1.0 - pout * pout / (2.0 * (double)m);
+    if (J.pearson) pout = isnan(pout) ? pout : isinf(pout) ? -INFINITY : 1.0 - pout * pout / (2.0 * (double)m);
     if (lane == 0) {
-        P[i] = (float)pout;
-        I[i] = iout;
+        gptr_w(J.P)[i] = (float)pout;
+        gptr_w(J.I)[i] = iout;
     }
 }
 
-template <typename T, int KS, int NB, int K>
-void launch_main(const MfmaPlan& p, const void* zq, const void* zd, const uint32_t* dmask,
-                 unsigned long long* cand, hipStream_t stream)
+template <typename T, int KS, int NB, int KH, int NW, int WPE>
+void launch_main(const MfmaJoinJob& one, const MfmaJoinJob* jobs, int njobs, int64_t blocks, hipStream_t stream)
 {
-    using V8 = typename Vec8<T>::type;
-    // four waves per SIMD where the 8-wave workgroup's 64 KB of LDS allows two
-    // workgroups per CU; the 4-wave workgroups of K-step 16 fit two per SIMD
-    constexpr int WPE = KS <= 8 ? 4 : 2;
-    hipLaunchKernelGGL((k_join_mfma<T, KS, NB, K, WPE>), dim3((unsigned)(p.npanels * p.nchunks)),
-                       dim3(kWave * waves_per_block(KS)), 0, stream, reinterpret_cast<const V8*>(zq), p.nqblk,
-                       reinterpret_cast<const V8*>(zd), dmask, p.ndblk, p.npanels, p.blk_per_chunk,
-                       (int)p.nchunks, cand);
+    hipLaunchKernelGGL((k_join_mfma<T, KS, NB, KH, NW, WPE>), dim3((unsigned)blocks), dim3(kWave * NW), 0, stream,
+                       one, jobs, njobs);
 }
 
-template <typename T, int KS, int NB>
-int launch_k(const MfmaPlan& p, const void* zq, const void* zd, const uint32_t* dmask, unsigned long long* cand,
-             hipStream_t stream)
+// K: candidates per row and chunk
+template <typename T, int KS, int NB, int NW, int WPE>
+int launch_k(int K, const MfmaJoinJob& one, const MfmaJoinJob* jobs, int njobs, int64_t blocks, hipStream_t stream)
 {
-    switch (p.K) {
-        case 1: launch_main<T, KS, NB, 1>(p, zq, zd, dmask, cand, stream); break;
-        case 2: launch_main<T, KS, NB, 2>(p, zq, zd, dmask, cand, stream); break;
-        case 4: launch_main<T, KS, NB, 4>(p, zq, zd, dmask, cand, stream); break;
-        case 8: launch_main<T, KS, NB, 8>(p, zq, zd, dmask, cand, stream); break;
-        default: return set_error(ABJ_EINVAL, "unsupported candidate count %d", p.K);
+    switch (K) {
+        case 4: launch_main<T, KS, NB, 4, NW, WPE>(one, jobs, njobs, blocks, stream); break;
+        case 8: launch_main<T, KS, NB, 8, NW, WPE>(one, jobs, njobs, blocks, stream); break;
+        default: return set_error(ABJ_EINVAL, "unsupported candidate count %d", K);
     }
     return ABJ_OK;
 }
 
+// Query blocks per wave (NB), waves per workgroup (NW) and the occupancy hint
+// (waves per SIMD) of each k-step count, the fastest of the shapes timed on
+// 262,144 x 262,144 random walks; must match mfma_shape() below.
 template <typename T>
-int launch_ks(const MfmaPlan& p, const void* zq, const void* zd, const uint32_t* dmask, unsigned long long* cand,
+int launch_ks(int KS, int K, const MfmaJoinJob& one, const MfmaJoinJob* jobs, int njobs, int64_t blocks,
               hipStream_t stream)
 {
-    switch (p.KS) {
-        case 2: return launch_k<T, 2, 1>(p, zq, zd, dmask, cand, stream);
-        case 4: return launch_k<T, 4, 1>(p, zq, zd, dmask, cand, stream);
-        case 8: return launch_k<T, 8, 1>(p, zq, zd, dmask, cand, stream);
-        case 16: return launch_k<T, 16, 1>(p, zq, zd, dmask, cand, stream);
-        default: return set_error(ABJ_EINVAL, "unsupported k-step count %d", p.KS);
+    switch (KS) {
+        case 1: return launch_k<T, 1, 1, 8, 4>(K, one, jobs, njobs, blocks, stream);
+        case 2: return launch_k<T, 2, 1, 8, 4>(K, one, jobs, njobs, blocks, stream);
+        case 4: return launch_k<T, 4, 1, 8, 4>(K, one, jobs, njobs, blocks, stream);
+        case 8: return launch_k<T, 8, 2, 4, 2>(K, one, jobs, njobs, blocks, stream);
+        case 16: return launch_k<T, 16, 1, 8, 2>(K, one, jobs, njobs, blocks, stream);
+        default: return set_error(ABJ_EINVAL, "unsupported k-step count %d", KS);
     }
 }
 
-template <typename T>
-void make_operand(const SeriesDev& s, int ks_n, int64_t nblk, void* out, hipStream_t stream)
+int launch_join(int tier, int KS, int K, const MfmaJoinJob& one, const MfmaJoinJob* jobs, int njobs, int64_t blocks,
+                hipStream_t stream)
 {
-    using V8 = typename Vec8<T>::type;
-    const int64_t nfrag = nblk * ks_n * kWave;
-    hipLaunchKernelGGL(k_make_operand<T>, dim3((unsigned)((nfrag + 255) / 256)), dim3(256), 0, stream, s.xc, s.mu,
-                       s.sig, s.flags, s.W, (int)s.m, ks_n, nfrag, reinterpret_cast<V8*>(out));
+    ABJ_TRY(tier == ABJ_TIER_BF16 ? launch_ks<__bf16>(KS, K, one, jobs, njobs, blocks, stream)
+                                  : launch_ks<_Float16>(KS, K, one, jobs, njobs, blocks, stream));
+    ABJ_HIP(hipGetLastError());
+    return ABJ_OK;
 }
 
+int launch_operand(int tier, const MfmaOpJob& one, const MfmaOpJob* jobs, int njobs, int64_t blocks,
+                   hipStream_t stream)
+{
+    if (blocks <= 0) return ABJ_OK;
+    if (tier == ABJ_TIER_BF16)
+        hipLaunchKernelGGL(k_make_operand<__bf16>, dim3((unsigned)blocks), dim3(256), 0, stream, one, jobs, njobs);
+    else
+        hipLaunchKernelGGL(k_make_operand<_Float16>, dim3((unsigned)blocks), dim3(256), 0, stream, one, jobs, njobs);
+    ABJ_HIP(hipGetLastError());
+    return ABJ_OK;
+}
+
+MfmaOpJob op_job(const SeriesDev& s, int ks_n, int64_t nblk, void* out, int64_t blk0)
+{
+    MfmaOpJob j{};
+    j.xc = s.xc;
+    j.mu = s.mu;
+    j.sig = s.sig;
+    j.flags = s.flags;
+    j.out = out;
+    j.W = s.W;
+    j.nfrag = nblk * ks_n * kWave;
+    j.blk0 = blk0;
+    j.m = s.m;
+    j.ks_n = ks_n;
+    return j;
+}
+
+int64_t op_blocks(const MfmaOpJob& j) { return (j.nfrag + 255) / 256; }
+
+MfmaJoinJob join_job(const MfmaPlan& p, const void* zq, const MfmaDictOp& dop, unsigned long long* cand,
+                     int64_t blk0)
+{
+    MfmaJoinJob j{};
+    j.zq = zq;
+    j.zd = dop.zd;
+    j.dmask = dop.dmask;
+    j.cand = cand;
+    j.nqblk = p.nqblk;
+    j.ndblk = p.ndblk;
+    j.npanels = p.npanels;
+    j.blk_per_chunk = p.blk_per_chunk;
+    j.nchunks = p.nchunks;
+    j.blk0 = blk0;
+    return j;
+}
+
+MfmaFinJob fin_job(const SeriesDev& A, const SeriesDev& B, const MfmaPlan& p, const unsigned long long* cand,
+                   int refine, int pearson, float* P, int64_t* I, int64_t blk0)
+{
+    MfmaFinJob j{};
+    j.axc = A.xc;
+    j.amu = A.mu;
+    j.asig = A.sig;
+    j.aflags = A.flags;
+    j.WA = A.W;
+    j.bxc = B.xc;
+    j.bmu = B.mu;
+    j.bsig = B.sig;
+    j.bflags = B.flags;
+    j.bfirst = B.first;
+    j.WB = B.W;
+    j.cand = cand;
+    j.P = P;
+    j.I = I;
+    j.blk0 = blk0;
+    j.ncand = (int32_t)(p.nchunks * p.K);
+    j.keep = p.keep;
+    j.m = A.m;
+    j.refine = refine;
+    j.pearson = pearson;
+    return j;
+}
+
+int64_t fin_blocks(const MfmaFinJob& j) { return (j.WA + kFinRows - 1) / kFinRows; }
+
 }  // namespace
+
+// NB and NW of each k-step count (see launch_ks).
+static void mfma_shape(int KS, int* nb, int* nw)
+{
+    *nb = KS == 8 ? 2 : 1;
+    *nw = KS == 8 ? 4 : 8;
+}
 
 int mfma_plan(int64_t WA, int64_t WB, int32_t m, int tier, int refine_k, MfmaPlan* p)
 {
     const int mp = (m + 15) / 16;
     int KS;
-    if (mp <= 2) KS = 2;
+    if (mp <= 1) KS = 1;
+    else if (mp <= 2) KS = 2;
     else if (mp <= 4) KS = 4;
     else if (mp <= 8) KS = 8;
     else if (mp <= 16) KS = 16;
     else return set_error(ABJ_EINVAL, "the BF16/FP16 tiers support m <= 256 (got %d)", m);
-    int K = refine_k <= 0 ? 4 : refine_k;
-    K = K <= 1 ? 1 : K <= 2 ? 2 : K <= 4 ? 4 : 8;
-    // one query block per wave: it leaves the registers for four waves per
-    // SIMD (K-steps <= 8), which hide the LDS and MFMA latencies of the sweep
-    const int NB = 1;
+    // keep: distinct picks re-checked per row; K: candidates per row and chunk
+    // (at least 4: short windows on quasi-periodic series have many near-equal
+    // 16-bit scores, and fewer candidates missed the best there)
+    int keep = refine_k <= 0 ? 4 : refine_k;
+    keep = keep <= 1 ? 1 : keep <= 2 ? 2 : keep <= 4 ? 4 : 8;
+    const int K = keep <= 4 ? 4 : 8;
+    int NB, NW;
+    mfma_shape(KS, &NB, &NW);
     p->tier = tier;
     p->KS = KS;
     p->K = K;
+    p->keep = keep;
     p->nqblk = (WA + 31) / 32;
     p->ndblk = (WB + 31) / 32;
-    const int64_t qblk_per_panel = (int64_t)waves_per_block(KS) * NB;
+    const int64_t qblk_per_panel = (int64_t)NW * NB;
     p->npanels = (p->nqblk + qblk_per_panel - 1) / qblk_per_panel;
     // split the dictionary sweep until there are enough workgroups to fill the
     // chip, but keep at least 64 blocks (2,048 windows) per chunk
@@ -559,51 +701,132 @@ int mfma_plan(int64_t WA, int64_t WB, int32_t m, int tier, int refine_k, MfmaPla
     return ABJ_OK;
 }
 
-size_t mfma_scratch_bytes(const MfmaPlan& p)
+size_t mfma_query_bytes(const MfmaPlan& p)
 {
     auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
-    size_t b = 0;
-    b += al((size_t)p.nqblk * p.KS * kWave * 16);  // query operand
-    b += al((size_t)p.ndblk * p.KS * kWave * 16);  // dictionary operand
-    b += al((size_t)p.ndblk * 4);                  // block masks
-    b += al((size_t)p.nqblk * 32 * p.nchunks * p.K * 8);  // candidates
-    return b;
+    return al((size_t)p.nqblk * p.KS * kWave * 16) +          // query operand
+           al((size_t)p.nqblk * 32 * p.nchunks * p.K * 8);    // candidates
+}
+
+size_t mfma_dict_bytes(const MfmaPlan& p)
+{
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    return al((size_t)p.ndblk * p.KS * kWave * 16) +  // dictionary operand
+           al((size_t)p.ndblk * 4);                   // block masks
+}
+
+int mfma_dict_build(const SeriesDev& B, const MfmaPlan& p, Arena& ar, MfmaDictOp* op, hipStream_t stream)
+{
+    void* zd = ar.take<char>((size_t)p.ndblk * p.KS * kWave * 16);
+    uint32_t* dmask = ar.take<uint32_t>((size_t)p.ndblk);
+    op->zd = zd;
+    op->dmask = dmask;
+    if (B.W <= 0 || p.ndblk <= 0) return ABJ_OK;
+    const MfmaOpJob oj = op_job(B, p.KS, p.ndblk, zd, 0);
+    ABJ_TRY(launch_operand(p.tier, oj, nullptr, 1, op_blocks(oj), stream));
+    hipLaunchKernelGGL(k_block_mask, dim3((unsigned)((p.ndblk + 255) / 256)), dim3(256), 0, stream, B.flags, B.W,
+                       p.ndblk, dmask);
+    ABJ_HIP(hipGetLastError());
+    return ABJ_OK;
 }
 
 int join_mfma_run(const SeriesDev& A, const SeriesDev& B, const MfmaPlan& p, int refine, int pearson, float* P,
-                  int64_t* I,
-                  Arena& ar, hipStream_t stream)
+                  int64_t* I, Arena& ar, hipStream_t stream, const MfmaDictOp* dop)
 {
     void* zq = ar.take<char>((size_t)p.nqblk * p.KS * kWave * 16);
-    void* zd = ar.take<char>((size_t)p.ndblk * p.KS * kWave * 16);
-    uint32_t* dmask = ar.take<uint32_t>((size_t)p.ndblk);
     unsigned long long* cand = ar.take<unsigned long long>((size_t)p.nqblk * 32 * p.nchunks * p.K);
+    MfmaDictOp own;
+    if (!dop) {
+        ABJ_TRY(mfma_dict_build(B, p, ar, &own, stream));
+        dop = &own;
+    }
     if (A.W <= 0) return ABJ_OK;
     if (B.W > 0) {
-        if (p.tier == ABJ_TIER_BF16) {
-            make_operand<__bf16>(A, p.KS, p.nqblk, zq, stream);
-            make_operand<__bf16>(B, p.KS, p.ndblk, zd, stream);
-        } else {
-            make_operand<_Float16>(A, p.KS, p.nqblk, zq, stream);
-            make_operand<_Float16>(B, p.KS, p.ndblk, zd, stream);
-        }
-        hipLaunchKernelGGL(k_block_mask, dim3((unsigned)((p.ndblk + 255) / 256)), dim3(256), 0, stream, B.flags, B.W,
-                           p.ndblk, dmask);
-        ABJ_HIP(hipGetLastError());
+        const MfmaOpJob oj = op_job(A, p.KS, p.nqblk, zq, 0);
+        ABJ_TRY(launch_operand(p.tier, oj, nullptr, 1, op_blocks(oj), stream));
+        const MfmaJoinJob jj = join_job(p, zq, *dop, cand, 0);
         ProfMark mark;
         ABJ_TRY(prof_begin(&mark, stream));
-        ABJ_TRY(p.tier == ABJ_TIER_BF16 ? launch_ks<__bf16>(p, zq, zd, dmask, cand, stream)
-                                        : launch_ks<_Float16>(p, zq, zd, dmask, cand, stream));
-        ABJ_HIP(hipGetLastError());
+        ABJ_TRY(launch_join(p.tier, p.KS, p.K, jj, nullptr, 1, p.npanels * p.nchunks, stream));
         ABJ_TRY(prof_end(&mark, stream, A.W * B.nvalid));
     } else {
         ABJ_TRY(fill_u64(cand, p.nqblk * 32 * p.nchunks * p.K, 0ull, stream));
     }
-    const int rows_per_block = 4;
-    hipLaunchKernelGGL(k_finalize_topk, dim3((unsigned)((A.W + rows_per_block - 1) / rows_per_block)),
-                       dim3(kWave * rows_per_block), 0, stream, A.xc, A.mu, A.sig, A.flags, A.W, B.xc, B.mu, B.sig,
-                       B.flags, B.first, B.W, (int)A.m, cand, (int)(p.nchunks * p.K), p.K, refine, pearson, P, I);
+    const MfmaFinJob fj = fin_job(A, B, p, cand, refine, pearson, P, I, 0);
+    hipLaunchKernelGGL(k_finalize_topk, dim3((unsigned)fin_blocks(fj)), dim3(kWave * kFinRows), 0, stream, fj,
+                       nullptr, 1);
     ABJ_HIP(hipGetLastError());
+    return ABJ_OK;
+}
+
+size_t mfma_batch_table_bytes(int n)
+{
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    return al(sizeof(MfmaOpJob) * (size_t)n) + al(sizeof(MfmaJoinJob) * (size_t)n) + al(sizeof(MfmaFinJob) * (size_t)n);
+}
+
+void mfma_batch_prepare(const MfmaBatchItem* items, int n, int tier, int refine, int pearson, void* host,
+                        MfmaBatchLaunch* L)
+{
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    char* h = static_cast<char*>(host);
+    *L = MfmaBatchLaunch();
+    L->tier = tier;
+    L->n = n;
+    L->off_join = al(sizeof(MfmaOpJob) * (size_t)n);
+    L->off_fin = L->off_join + al(sizeof(MfmaJoinJob) * (size_t)n);
+    MfmaOpJob* oj = reinterpret_cast<MfmaOpJob*>(h);
+    MfmaJoinJob* jj = reinterpret_cast<MfmaJoinJob*>(h + L->off_join);
+    MfmaFinJob* fj = reinterpret_cast<MfmaFinJob*>(h + L->off_fin);
+    // operand and re-check jobs in item order; join jobs grouped by (k steps,
+    // candidates), one launch per group
+    int64_t ob = 0, fb = 0;
+    for (int a = 0; a < n; ++a) {
+        const MfmaBatchItem& it = items[a];
+        const bool sweep = it.B->W > 0 && it.A.W > 0;
+        oj[a] = op_job(it.A, it.plan.KS, sweep ? it.plan.nqblk : 0, it.zq, ob);
+        ob += op_blocks(oj[a]);
+        fj[a] = fin_job(it.A, *it.B, it.plan, it.cand, refine, pearson, it.P, it.I, fb);
+        fb += fin_blocks(fj[a]);
+        if (!sweep && it.A.W > 0) L->empty.push_back(a);
+        if (!sweep) continue;
+        size_t g = 0;
+        while (g < L->groups.size() && !(L->groups[g].ks == it.plan.KS && L->groups[g].k == it.plan.K)) ++g;
+        if (g == L->groups.size()) L->groups.push_back({it.plan.KS, it.plan.K, 0, 0, 0});
+    }
+    L->op_blocks = ob;
+    L->fin_blocks = fb;
+    int w = 0;
+    for (auto& gr : L->groups) {
+        gr.first = w;
+        int64_t blk = 0;
+        for (int a = 0; a < n; ++a) {
+            const MfmaBatchItem& it = items[a];
+            if (it.B->W <= 0 || it.A.W <= 0 || it.plan.KS != gr.ks || it.plan.K != gr.k) continue;
+            jj[w++] = join_job(it.plan, it.zq, it.dop, it.cand, blk);
+            blk += it.plan.npanels * it.plan.nchunks;
+        }
+        gr.count = w - gr.first;
+        gr.blocks = blk;
+    }
+}
+
+int mfma_batch_launch(const MfmaBatchItem* items, const void* dev, const MfmaBatchLaunch& L, hipStream_t stream)
+{
+    const char* d = static_cast<const char*>(dev);
+    for (int e : L.empty) {
+        const MfmaBatchItem& it = items[e];
+        ABJ_TRY(fill_u64(it.cand, it.plan.nqblk * 32 * it.plan.nchunks * it.plan.K, 0ull, stream));
+    }
+    ABJ_TRY(launch_operand(L.tier, MfmaOpJob{}, reinterpret_cast<const MfmaOpJob*>(d), L.n, L.op_blocks, stream));
+    const MfmaJoinJob* jj = reinterpret_cast<const MfmaJoinJob*>(d + L.off_join);
+    for (const auto& gr : L.groups)
+        ABJ_TRY(launch_join(L.tier, gr.ks, gr.k, MfmaJoinJob{}, jj + gr.first, gr.count, gr.blocks, stream));
+    if (L.fin_blocks > 0) {
+        hipLaunchKernelGGL(k_finalize_topk, dim3((unsigned)L.fin_blocks), dim3(kWave * kFinRows), 0, stream,
+                           MfmaFinJob{}, reinterpret_cast<const MfmaFinJob*>(d + L.off_fin), L.n);
+        ABJ_HIP(hipGetLastError());
+    }
     return ABJ_OK;
 }
 

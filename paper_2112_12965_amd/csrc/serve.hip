@@ -41,6 +41,11 @@ struct DictM {
     int32_t m = 0;
     SeriesDev B;
     void* mem = nullptr;
+    // the 16-bit tiers' dictionary side (operand fragments and block masks),
+    // one per tier (0 = BF16, 1 = FP16), built at its first use
+    mutable void* op_mem[2] = {nullptr, nullptr};
+    mutable MfmaDictOp op[2];
+    mutable hipEvent_t op_ready[2] = {nullptr, nullptr};
 };
 }  // namespace abj
 
@@ -48,9 +53,11 @@ struct abj_dict {
     int device = 0;
     int64_t n = 0;
     std::vector<int64_t> bounds;
+    std::vector<int64_t> orig_start;  // per segment: its first sample in the source series (empty: not given)
     double* x = nullptr;
     int64_t* dbounds = nullptr;
     std::vector<DictM> per_m;
+    mutable std::mutex op_mu;  // guards the lazily built 16-bit dictionary sides
     const DictM* find(int32_t m) const
     {
         for (auto& e : per_m)
@@ -62,12 +69,58 @@ struct abj_dict {
 static void dict_release(abj_dict* d)
 {
     if (!d) return;
-    for (auto& e : d->per_m)
+    for (auto& e : d->per_m) {
         if (e.mem) (void)hipFree(e.mem);
+        for (int t = 0; t < 2; ++t) {
+            if (e.op_ready[t]) (void)hipEventDestroy(e.op_ready[t]);
+            if (e.op_mem[t]) (void)hipFree(e.op_mem[t]);
+        }
+    }
     if (d->x) (void)hipFree(d->x);
     if (d->dbounds) (void)hipFree(d->dbounds);
     delete d;
 }
+
+namespace {
+// The 16-bit dictionary side of window length e->m for `tier`: built on
+// `stream` at its first use (one device allocation, kept until the dictionary
+// is freed); a later caller on another stream waits for the build's event.
+int dict_operand(const abj_dict* d, const DictM* e, int tier, hipStream_t stream, MfmaDictOp* out)
+{
+    const int t = tier == ABJ_TIER_BF16 ? 0 : 1;
+    std::lock_guard<std::mutex> lk(d->op_mu);
+    if (!e->op_mem[t]) {
+        MfmaPlan p;
+        ABJ_TRY(mfma_plan(1, e->B.W, e->m, tier, 0, &p));
+        const size_t bytes = mfma_dict_bytes(p);
+        void* mem = nullptr;
+        if (hipMalloc(&mem, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return set_error(ABJ_ENOMEM, "dictionary operand of %zu bytes", bytes);
+        }
+        Arena ar(mem, bytes);
+        MfmaDictOp op;
+        hipEvent_t ev = nullptr;
+        int rc = mfma_dict_build(e->B, p, ar, &op, stream);
+        if (rc == ABJ_OK && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
+            rc = set_error(ABJ_EHIP, "event creation failed");
+        if (rc == ABJ_OK && hipEventRecord(ev, stream) != hipSuccess) rc = set_error(ABJ_EHIP, "event record failed");
+        if (rc != ABJ_OK) {
+            (void)hipStreamSynchronize(stream);
+            if (ev) (void)hipEventDestroy(ev);
+            (void)hipFree(mem);
+            return rc;
+        }
+        e->op_mem[t] = mem;
+        e->op[t] = op;
+        e->op_ready[t] = ev;
+    } else {
+        ABJ_HIP(hipStreamWaitEvent(stream, e->op_ready[t], 0));
+    }
+    *out = e->op[t];
+    return ABJ_OK;
+}
+}  // namespace
 
 extern "C" int abj_dict_create(const double* dict, int64_t n_dict, const int64_t* seg_bounds, int32_t n_seg,
                                const int32_t* ms, int32_t n_ms, abj_dict** out)
@@ -175,7 +228,10 @@ extern "C" int ab_join_dict(const abj_dict* d, const double* query, int64_t n_qu
         o.tier == ABJ_TIER_FP32 && e->B.W > 0 ? fp32_partial_bytes(WA, e->B.nchunks) : 0;
     ar.reserve(query_scratch_bytes(n_query, m, e->B.W, o, plan) + part_bytes);
     ABJ_TRY(ar.commit());
-    return join_query(query, n_query, m, e->B, o, plan, P_AB, I_AB, ar, stream, part_bytes);
+    MfmaDictOp dop;
+    if (o.tier != ABJ_TIER_FP32) ABJ_TRY(dict_operand(d, e, o.tier, stream, &dop));
+    return join_query(query, n_query, m, e->B, o, plan, P_AB, I_AB, ar, stream, part_bytes,
+                      o.tier != ABJ_TIER_FP32 ? &dop : nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -341,7 +397,9 @@ int grow_pinned(abj_server* s, char** p, size_t* have, size_t want)
 // so that one copy brings the queries and descriptors in and one copy takes
 // the results out.  FP32 requests then take four statistics launches, one
 // persistent tile launch and one row-epilogue launch for the whole batch; the
-// 16-bit tiers run one join per request inside the same buffer.
+// 16-bit tiers take the same statistics launches, one launch for every query
+// operand, one matrix-core sweep per k-step count present in the batch (the
+// window lengths of the requests) and one re-check launch.
 int launch_batch(abj_server* s, Batch& b)
 {
     hipStream_t st = s->stream;
@@ -350,7 +408,8 @@ int launch_batch(abj_server* s, Batch& b)
     const bool fp32 = s->jo.tier == ABJ_TIER_FP32;
     const size_t t_stats = al256(stats_job_bytes() * k), t_slots = al256(sizeof(Fp32Slot) * k),
                  t_fin = al256(finalize_job_bytes() * k);
-    const size_t tables = fp32 ? t_stats + t_slots + t_fin + kTileCounterBytes : 0;
+    const size_t t_mfma = fp32 ? 0 : mfma_batch_table_bytes((int)k);
+    const size_t tables = fp32 ? t_stats + t_slots + t_fin + kTileCounterBytes : t_stats + t_mfma;
     size_t qbytes = 0, pbytes = 0, ibytes = 0, work = 0;
     for (Req* r : b.reqs) {
         qbytes += al256(sizeof(double) * (size_t)r->n);
@@ -361,7 +420,8 @@ int launch_batch(abj_server* s, Batch& b)
     const size_t up = tables + qbytes, down = pbytes + ibytes;
     const size_t slots = (size_t)s->o.max_slots;
     const size_t cap = (size_t)s->o.mem_budget + al256(stats_job_bytes() * slots) + al256(sizeof(Fp32Slot) * slots) +
-                       al256(finalize_job_bytes() * slots) + kTileCounterBytes;
+                       al256(finalize_job_bytes() * slots) + kTileCounterBytes +
+                       (fp32 ? 0 : mfma_batch_table_bytes((int)slots));
     ABJ_TRY(grow_device(&sb.dev, &sb.dev_bytes, up + down + work, cap, st));
     ABJ_TRY(grow_pinned(s, &sb.hin, &sb.hin_bytes, up));
     {
@@ -381,6 +441,7 @@ int launch_batch(abj_server* s, Batch& b)
     size_t qo = tables, po = up, io = up + pbytes, wo = up + down;
     int64_t blk_sum = 0, blk_loc = 0, blk_win = 0, blk_fin = 0, tiles = 0, pairs = 0;
     int max_m = 2;
+    std::vector<MfmaBatchItem> items(fp32 ? 0 : k);
     for (size_t a = 0; a < k; ++a) {
         Req* r = b.reqs[a];
         memcpy(H + qo, r->q_borrowed ? r->q_borrowed : r->q.data(), sizeof(double) * (size_t)r->n);
@@ -395,8 +456,24 @@ int launch_batch(abj_server* s, Batch& b)
         r->work = D + wo;
         r->work_bytes = query_scratch_bytes(r->n, r->m, r->dm->B.W, s->jo, r->plan);
         wo += r->work_bytes;
-        if (!fp32) continue;
         Arena ar(r->work, r->work_bytes);
+        if (!fp32) {
+            // 16-bit tiers: statistics in the batch's statistics launches,
+            // then the query operand and candidates; the dictionary side of
+            // the request's window length is built once and kept
+            stats_carve_job(ar, r->dq, r->n, r->m, &r->A, nullptr, H + a * stats_job_bytes(), &blk_sum, &blk_loc,
+                            &blk_win);
+            MfmaBatchItem& it = items[a];
+            it.A = r->A;
+            it.B = &r->dm->B;
+            it.plan = r->plan;
+            it.zq = ar.take<char>((size_t)r->plan.nqblk * r->plan.KS * 64 * 16);
+            it.cand = ar.take<unsigned long long>((size_t)r->plan.nqblk * 32 * r->plan.nchunks * r->plan.K);
+            it.P = r->dP;
+            it.I = r->dI;
+            ABJ_TRY(dict_operand(s->d, r->dm, s->jo.tier, st, &it.dop));
+            continue;
+        }
         const size_t key_bytes = sizeof(unsigned long long) * (size_t)r->W;
         r->keys = ar.take<unsigned long long>(key_bytes / sizeof(unsigned long long));
         stats_carve_job(ar, r->dq, r->n, r->m, &r->A, r->keys, H + a * stats_job_bytes(), &blk_sum, &blk_loc,
@@ -411,6 +488,8 @@ int launch_batch(abj_server* s, Batch& b)
                      &blk_fin);
     }
     if (fp32) memset(H + tables - kTileCounterBytes, 0, kTileCounterBytes);  // tile counters
+    MfmaBatchLaunch L;
+    if (!fp32) mfma_batch_prepare(items.data(), (int)k, s->jo.tier, 1, 0, H + t_stats, &L);
     ABJ_HIP(hipMemcpyAsync(D, H, up, hipMemcpyHostToDevice, st));
     if (fp32) {
         ABJ_TRY(stats_launch_many(D, (int)k, blk_sum, blk_loc, blk_win, st));
@@ -419,10 +498,8 @@ int launch_batch(abj_server* s, Batch& b)
                                 true));
         ABJ_TRY(finalize_launch_many(D + t_stats + t_slots, (int)k, blk_fin, st));
     } else {
-        for (Req* r : b.reqs) {
-            Arena ar(r->work, r->work_bytes);
-            ABJ_TRY(join_query(r->dq, r->n, r->m, r->dm->B, s->jo, r->plan, r->dP, r->dI, ar, st));
-        }
+        ABJ_TRY(stats_launch_many(D, (int)k, blk_sum, blk_loc, blk_win, st));
+        ABJ_TRY(mfma_batch_launch(items.data(), D + t_stats, L, st));
     }
     ABJ_HIP(hipMemcpyAsync(b.hout, b.dout, down, hipMemcpyDeviceToHost, st));
     ABJ_HIP(hipEventCreateWithFlags(&b.ev, hipEventDisableTiming));

@@ -1,21 +1,31 @@
 #!/usr/bin/env python3
 """Benchmark of the AB-join hot path on one MI355X.
 
-One step = one full ``ab_join`` call (window statistics, pair loop, row
-reduction, FP64 winner re-check) of the dictionary inference workload:
-an ECG-like query of 131,072 samples against a dictionary of 16 segments x
-2,000 samples, m = 256 (windows that cross a segment break are masked).
-Inputs are resident in device memory before the timed region.
+Headline workload (default): the large AB-join of two 1,048,576-sample
+Gaussian random walks at m = 128, run by the three tiers of the library: the
+plain FP32 diagonal join and the BF16 / FP16 matrix-core joins with their FP64
+re-check.  One step = one full ``ab_join`` call (window statistics, pair
+scores, row reduction, FP64 re-check); inputs are resident in device memory
+before the timed region.  Every tier is timed over the same number of steps.
 
-Prints ONE JSON line.  ``value`` = valid (query window, dictionary window)
-pairs per second over the timed steps.  ``roofline`` is for the pair-loop
-kernel, timed with HIP events that the library records on the stream it
-launches the kernel on.  ``cpu_baseline`` is the FP64 oracle on a bounded
-sample of query rows of the same workload, on the host cores.
+Prints ONE JSON line.  ``value`` = valid (query window, reference window)
+pairs per second of the fastest tier whose error against the FP64 oracle on a
+4,096-row sample stays within the stated bar (|P - P_oracle| <= 1e-3 after
+refinement); without the CPU leg (--no-cpu) the FP32 tier's.  ``roofline`` is
+for that tier's pair-score kernel, timed with HIP events that the library
+records on the stream it launches the kernel on.  ``cpu_baseline`` is the FP64
+oracle on the same 4,096 sampled rows, on the host cores.
+
+Extra keys: every tier's rate, roofline and error before and after
+refinement (``tiers``), the dictionary workload (``dictionary_workload``),
+the tiers on short windows (``tiers_short_windows``), serving
+(``serving``) and the whole method at the database workload's size
+(``pipeline``), each with its check against the oracle.
 """
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -26,15 +36,27 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-WORKLOAD = "ecg131k_dict16x2000_m256"
+WORKLOAD = "rw1m_m128"
+DICT_WORKLOAD = "ecg131k_dict16x2000_m256"
+METRIC = "AB-join subsequence-pair distances/s vs plain FP32 at stated error; p99 latency"
+TOL = 1e-3  # the stated bar: |P - P_oracle| per result
 # issue ceiling of FMA-class VALU instructions (FP32 FMA and multiply, FP64 FMA)
 # without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 VALU_LANE_INSTR_PER_S = 256 * 4 * 16 * 2.4e9
-METRIC = "AB-join subsequence-pair distances/s vs plain FP32 at stated error; p99 latency"
 # FP32 vector peak of MI355X: 256 CUs x 128 FP32 lanes x 2 flops (FMA) x 2.4 GHz
 FP32_PEAK = 157.3e12
-# per pair: 2 FMA (diagonal covariance step) + 1 multiply (column weight) + 1 max (running best)
-FLOPS_PER_PAIR = 2 * 2 + 1 + 1
+# dense BF16 / FP16 matrix-core peak of MI355X
+MFMA_PEAK = 2.5e15
+# FP32 tier, per pair: 2 FMA (diagonal covariance step) + 1 multiply (column weight) + 1 max
+FLOPS_PER_PAIR_FP32 = 2 * 2 + 1 + 1
+TIER_NAMES = ("fp32", "bf16", "fp16")
+KERNEL_SRC = {"fp32": os.path.join(ROOT, "paper_2112_12965_amd", "csrc", "join_fp32.hip"),
+              "bf16": os.path.join(ROOT, "paper_2112_12965_amd", "csrc", "join_mfma.hip"),
+              "fp16": os.path.join(ROOT, "paper_2112_12965_amd", "csrc", "join_mfma.hip")}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def profiled_field(kernel_source: str, summary: str, field: str):
@@ -52,53 +74,165 @@ def profiled_field(kernel_source: str, summary: str, field: str):
     return None
 
 
+def summary_path(tier, workload, kind):
+    kern = "k_join_fp32" if tier == "fp32" else f"k_join_mfma_{tier}"
+    return os.path.join(ROOT, "profiles", f"{kern}_{workload}_{kind}_counters.md")
+
+
 def valid_windows(bounds, m):
     b = np.asarray(bounds)
     return int(sum(max(0, int(b[s + 1] - b[s]) - m + 1) for s in range(len(b) - 1)))
 
 
-def cpu_baseline(w, results, target_s: float, threads: int):
-    """Time the FP64 oracle on a bounded row sample; report each GPU tier's error there.
+def host_cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
 
-    ``results``: {tier: (P, I)} host arrays of the full GPU result.  The oracle
-    is timed on a 64-row call first, then on as many rows as fit in about
-    ``target_s`` seconds."""
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def time_join(abjoin, q, d, bounds, m, tier, steps, warmup, P, I, no_refine=False):
+    """Seconds per whole step and the kernel's milliseconds and valid pairs per launch (HIP events)."""
+    import torch
+
+    L = abjoin.lib()
+    for _ in range(warmup):
+        abjoin.ab_join(q, d, bounds, m, tier=tier, out=(P, I), no_refine=no_refine)
+    torch.cuda.synchronize()
+    L.abj_profile_enable(1)
+    L.abj_profile_read(None, None, None)  # clear
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        abjoin.ab_join(q, d, bounds, m, tier=tier, out=(P, I), no_refine=no_refine)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    kms, nl, kp = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64()
+    L.abj_profile_read(ctypes.byref(kms), ctypes.byref(nl), ctypes.byref(kp))
+    L.abj_profile_enable(0)
+    return dt, kms.value / max(nl.value, 1), kp.value / max(nl.value, 1)
+
+
+def roofline(tier, m, workload, kernel_ms, kernel_pairs):
+    """The tier's pair-score kernel against its peak: FP32 VALU for the FP32
+    tier (6 flops per pair), dense BF16/FP16 matrix cores for the 16-bit tiers
+    (2m flops per pair, the window products).  Counter-based figures come from
+    the committed summaries while the kernel source is the profiled one."""
+    src = KERNEL_SRC[tier]
+    rate = kernel_pairs / (kernel_ms * 1e-3)
+    if tier == "fp32":
+        achieved = FLOPS_PER_PAIR_FP32 * rate
+        out = {"bound": "alu", "kernel": "k_join_fp32_batch", "achieved": achieved / 1e12, "peak": FP32_PEAK / 1e12,
+               "unit": "TFLOP/s", "frac": achieved / FP32_PEAK, "flops_per_pair": FLOPS_PER_PAIR_FP32,
+               "kernel_ms": kernel_ms,
+               "traffic": profiled_field(src, summary_path(tier, workload, "hbm"), "traffic_bytes_per_launch")}
+        # the same kernel against the issue ceiling of its FMA-class
+        # instructions, with their lane-instructions per pair (FP64 edges
+        # included) from the committed counters
+        fpp = profiled_field(src, summary_path(tier, workload, "valu_types"), "fma_class_lane_instructions_per_pair")
+        vpp = profiled_field(src, summary_path(tier, workload, "valu_types"), "valu_lane_instructions_per_pair")
+        out["valu_issue"] = None if fpp is None else {
+            "fma_class_lane_instructions_per_pair": fpp, "all_valu_lane_instructions_per_pair": vpp,
+            "ceiling_lane_instructions_per_s": VALU_LANE_INSTR_PER_S,
+            "frac": rate * fpp / VALU_LANE_INSTR_PER_S}
+        return out
+    achieved = 2.0 * m * rate
+    return {"bound": "mfma", "kernel": "k_join_mfma", "achieved": achieved / 1e12, "peak": MFMA_PEAK / 1e12,
+            "unit": "TFLOP/s", "frac": achieved / MFMA_PEAK, "flops_per_pair": 2 * m, "kernel_ms": kernel_ms,
+            "traffic": profiled_field(src, summary_path(tier, workload, "hbm"), "traffic_bytes_per_launch"),
+            "mfma_busy_frac": profiled_field(src, summary_path(tier, workload, "mfma"), "mfma_busy_frac")}
+
+
+def error_stats(P, I, Po, Io, P2o):
+    """|P - P_oracle| and index agreement on rows whose best-to-second gap exceeds the bar."""
+    P = np.asarray(P, dtype=np.float64)
+    fin = np.isfinite(Po)
+    err = np.abs(P[fin] - Po[fin])
+    clear = fin & ((P2o - Po) > TOL)
+    return {"rows": int(len(Po)), "max_abs": float(err.max()) if err.size else 0.0,
+            "mean_abs": float(err.mean()) if err.size else 0.0,
+            "index_match_clear_rows": float(np.mean(I[clear] == Io[clear])) if clear.any() else 1.0}
+
+
+def headline(abjoin, synth, args):
+    """The headline workload: every tier timed over --steps; results kept for the oracle check."""
+    import torch
+
+    w = synth.WORKLOADS[args.workload]()
+    m, bounds = w["m"], w["bounds"]
+    q = torch.from_numpy(w["query"]).cuda()
+    d = torch.from_numpy(w["dict"]).cuda()
+    WA = len(w["query"]) - m + 1
+    pairs = WA * valid_windows(bounds, m)
+    tiers, results = {}, {}
+    for tier in (("fp32",) if args.no_tiers else TIER_NAMES):
+        P = torch.empty(WA, dtype=torch.float32, device="cuda")
+        I = torch.empty(WA, dtype=torch.int64, device="cuda")
+        dt, kms, kpairs = time_join(abjoin, q, d, bounds, m, tier, args.steps, args.warmup, P, I)
+        rec = {"pairs_per_s": pairs / dt, "ms_per_step": dt * 1e3, "steps": args.steps,
+               "roofline": roofline(tier, m, args.workload, kms, kpairs)}
+        results[tier] = (P.cpu().numpy(), I.cpu().numpy())
+        if tier != "fp32":
+            # the tier's error before refinement: the distance implied by the best 16-bit score
+            Pu = torch.empty_like(P)
+            Iu = torch.empty_like(I)
+            abjoin.ab_join(q, d, bounds, m, tier=tier, out=(Pu, Iu), no_refine=True)
+            torch.cuda.synchronize()
+            results[tier + "_unrefined"] = (Pu.cpu().numpy(), Iu.cpu().numpy())
+        tiers[tier] = rec
+        log(f"{args.workload} {tier}: {rec['pairs_per_s']:.3e} pairs/s, {dt * 1e3:.2f} ms/step")
+    for tier in tiers:
+        tiers[tier]["vs_fp32"] = tiers[tier]["pairs_per_s"] / tiers["fp32"]["pairs_per_s"]
+    del q, d
+    torch.cuda.empty_cache()
+    return w, pairs, tiers, results
+
+
+def oracle_leg(w, results, tiers, rows, threads):
+    """The FP64 oracle on `rows` random query rows of the workload: each
+    tier's error there (after and, for the 16-bit tiers, before refinement),
+    and the oracle's own rate (the CPU baseline)."""
     import oracle
 
     q, d, b, m = w["query"], w["dict"], w["bounds"], w["m"]
     W = len(q) - m + 1
     V = valid_windows(b, m)
-    rng = np.random.default_rng(12345)
+    sample = np.sort(np.random.default_rng(12345).choice(W, min(rows, W), replace=False))
     t0 = time.perf_counter()
-    oracle.ab_join(q, d, b, m, rows=np.sort(rng.choice(W, 64, replace=False)), threads=threads)
-    t64 = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    oracle.ab_join(q, d, b, m, rows=np.sort(rng.choice(W, 256, replace=False)), threads=threads)
-    t256 = time.perf_counter() - t0
-    per_row = max((t256 - t64) / 192.0, 1e-6)  # the call's fixed cost cancels
-    nrows = int(np.clip(target_s / per_row, 256, W))
-    rows = np.sort(rng.choice(W, nrows, replace=False))
-    t0 = time.perf_counter()
-    Po, Io, P2o = oracle.ab_join(q, d, b, m, rows=rows, threads=threads, second=True)
+    Po, Io, P2o = oracle.ab_join(q, d, b, m, rows=sample, threads=threads, second=True)
     dt = time.perf_counter() - t0
-    errs = {}
-    for tier, (P, I) in results.items():
-        err = np.abs(P[rows].astype(np.float64) - Po)
-        clear = (P2o - Po) > 1e-3
-        errs[tier] = {"rows": nrows, "max_abs": float(err.max()), "mean_abs": float(err.mean()),
-                      "index_match_clear_rows": float(np.mean(I[rows][clear] == Io[clear]))}
-    return (
-        {"value": nrows * V / dt, "unit": "pair-distances/s", "cores": threads, "kind": "oracle",
-         "sample": f"{nrows} random query rows x {V} dictionary windows of the same workload, "
-                   f"{dt:.1f} s wall, FP64 brute force, OpenMP {threads} threads"},
-        errs,
-    )
+    for tier, rec in tiers.items():
+        P, I = results[tier]
+        rec["error_vs_oracle"] = error_stats(P[sample], I[sample], Po, Io, P2o)
+        if tier + "_unrefined" in results:
+            Pu, Iu = results[tier + "_unrefined"]
+            rec["error_vs_oracle_before_refinement"] = error_stats(Pu[sample], Iu[sample], Po, Io, P2o)
+    # single-thread rate on a small sample of the same rows
+    s1 = sample[:: max(1, len(sample) // 32)][:32]
+    t1 = time.perf_counter()
+    oracle.ab_join(q, d, b, m, rows=s1, threads=1)
+    dt1 = time.perf_counter() - t1
+    cb = {"value": len(sample) * V / dt, "unit": "pair-distances/s", "cores": threads, "kind": "oracle",
+          "sample": f"{len(sample)} random query rows x {V} reference windows of the {w.get('name', 'workload')} "
+                    f"workload, {dt:.1f} s wall, FP64 brute force, OpenMP {threads} threads",
+          "cpu_model": cpu_model(), "host_cores": host_cores(),
+          "single_thread": {"value": len(s1) * V / dt1, "unit": "pair-distances/s", "cores": 1,
+                            "sample": f"{len(s1)} of the same rows, {dt1:.1f} s"}}
+    return cb
 
 
-def short_windows(abjoin, synth, ms=(16, 32, 64), n=262144, rows=192):
-    """Tiers against short windows: whole-step pairs/s of every tier on two
-    n-sample random walks per m.  Returns the record and, for the CPU leg's
-    error check, each tier's result on `rows` random query rows."""
+def short_windows(abjoin, synth, ms, n, steps, rows=192):
+    """All three tiers on two n-sample random walks per m (whole step), and
+    each tier's result on `rows` random query rows for the oracle check."""
     import torch
 
     rng = synth.rng_for(7, 0)
@@ -111,16 +245,22 @@ def short_windows(abjoin, synth, ms=(16, 32, 64), n=262144, rows=192):
         rec = {}
         sample = np.sort(np.random.default_rng(100 + m).choice(W, rows, replace=False))
         got = {}
-        for tier in ("fp32", "bf16", "fp16"):
+        for tier in TIER_NAMES:
             P = torch.empty(W, dtype=torch.float32, device="cuda")
             I = torch.empty(W, dtype=torch.int64, device="cuda")
-            dt = time_tier(abjoin, a, b, [0, n], m, tier, 5, 2, P, I)
-            rec[tier] = {"pairs_per_s": W * W / dt, "ms_per_step": dt * 1e3}
+            dt, kms, kpairs = time_join(abjoin, a, b, [0, n], m, tier, steps, 1, P, I)
+            rec[tier] = {"pairs_per_s": W * W / dt, "ms_per_step": dt * 1e3,
+                         "kernel_pairs_per_s": kpairs / (kms * 1e-3)}
+            if tier != "fp32":
+                rec[tier]["roofline_frac"] = 2.0 * m * kpairs / (kms * 1e-3) / MFMA_PEAK
             got[tier] = (P.cpu().numpy().astype(np.float64)[sample], I.cpu().numpy()[sample])
         for tier in ("bf16", "fp16"):
             rec[tier]["vs_fp32"] = rec[tier]["pairs_per_s"] / rec["fp32"]["pairs_per_s"]
         out["m"][str(m)] = rec
         samples[m] = (sample, got)
+        log(f"short windows m={m}: bf16 x{rec['bf16']['vs_fp32']:.2f}, fp16 x{rec['fp16']['vs_fp32']:.2f} of fp32")
+    del a, b
+    torch.cuda.empty_cache()
     return out, (a_h, b_h, samples)
 
 
@@ -132,102 +272,48 @@ def short_window_errors(record, data, threads):
     n = len(a_h)
     for m, (rows, got) in samples.items():
         Po, Io, P2o = oracle.ab_join(a_h, b_h, [0, n], m, rows=rows, threads=threads, second=True)
-        clear = (P2o - Po) > 1e-3
         for tier, (Pg, Ig) in got.items():
-            r = record["m"][str(m)][tier]
-            r["rows_checked"] = int(len(rows))
-            r["max_abs_err"] = float(np.abs(Pg - Po).max())
-            r["index_match_clear_rows"] = float(np.mean(Ig[clear] == Io[clear])) if clear.any() else 1.0
+            record["m"][str(m)][tier]["error_vs_oracle"] = error_stats(Pg, Ig, Po, Io, P2o)
 
 
-def pipeline(abjoin, synth, n=262144, n_series=8, m=256, space_saving=0.9, K=50):
-    """The whole method at the size of the database workload: the learning
-    phase (Alg. 1) on each of n_series ECG-like database series, their
-    dictionaries concatenated into one, each of n_series held-out series (50
-    planted anomalous beats) joined against it (Alg. 2), and its exact top-K
-    discords against the whole database from that join (Lemmas 1-2).  e_max is
-    the largest of the per-series values, an upper bound for the concatenated
-    dictionary.  Reports the time of each phase and how many planted beats the
-    discords hit (a discord within one beat, 260 samples, of a planted start)."""
+def dictionary_workload(abjoin, synth, steps, warmup):
+    """The dictionary inference workload (ECG-like 131,072-sample query against
+    16 x 2,000-sample dictionary segments, m = 256): every tier's whole step
+    and the FP32 kernel's roofline."""
     import torch
 
-    db = [synth.ecg_like(n, synth.rng_for(11, k)) for k in range(n_series)]
-    held = [synth.ecg_like(n, synth.rng_for(12, k), n_anomalies=50, return_anomalies=True) for k in range(n_series)]
-    db_dev = [torch.from_numpy(x).cuda() for x in db]
-    held_dev = [torch.from_numpy(x).cuda() for x, _ in held]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    learned = [abjoin.dict_build(x, m, stop="space_saving", value=space_saving) for x in db_dev]
-    torch.cuda.synchronize()
-    t_learn = time.perf_counter() - t0
-    D = torch.cat([g["dictionary"] for g in learned])
-    dbounds = [0]
-    for g in learned:
-        dbounds += [dbounds[-1] + int(b) for b in g["bounds"][1:]]
-    e_max = max(g["e_max"] for g in learned)
-    ref = torch.cat(db_dev)
-    rbounds = [k * n for k in range(n_series + 1)]
-    W = n - m + 1
-    V = valid_windows(dbounds, m)
-    t0 = time.perf_counter()
-    joined = [abjoin.ab_join(q, D, dbounds, m) for q in held_dev]
-    torch.cuda.synchronize()
-    t_join = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    found = [abjoin.discords(q, Ph, e_max, ref, rbounds, m, K) for q, (Ph, _) in zip(held_dev, joined)]
-    torch.cuda.synchronize()
-    t_disc = time.perf_counter() - t0
-    hits = 0
-    for (_, starts), r in zip(held, found):
-        for row in r["rows"]:
-            hits += int(np.any(np.abs(starts - int(row)) <= 260))
-    # for the CPU leg's check: the first held-out series, its dictionary join
-    # and its discords, with the dictionary and the database on the host
-    check = (held[0][0], D.cpu().numpy(), np.asarray(dbounds), np.concatenate(db), np.asarray(rbounds), m,
-             joined[0][0].cpu().numpy().astype(np.float64), joined[0][1].cpu().numpy(), found[0])
-    return check, {"database": f"{n_series} x {n} ECG-like", "held_out": f"{n_series} x {n}, 50 planted beats each",
-            "m": m, "space_saving": space_saving, "K": K,
-            "dictionary_samples": int(D.numel()), "dictionary_segments": len(dbounds) - 1, "e_max": e_max,
-            "learn_ms_per_series": t_learn * 1e3 / n_series,
-            "join_ms_per_series": t_join * 1e3 / n_series, "join_pairs_per_s": n_series * W * V / t_join,
-            "discords_ms_per_series": t_disc * 1e3 / n_series,
-            "exact_rows_fraction": float(np.mean([r["rows_exact"] / W for r in found])),
-            "rounds": [int(r["rounds"]) for r in found], "certified_bits": [int(r["certified"]) for r in found],
-            "discords_on_planted_beats": f"{hits} of {n_series * K}"}
+    w = synth.WORKLOADS[DICT_WORKLOAD]()
+    m, bounds = w["m"], w["bounds"]
+    q = torch.from_numpy(w["query"]).cuda()
+    d = torch.from_numpy(w["dict"]).cuda()
+    WA = len(w["query"]) - m + 1
+    pairs = WA * valid_windows(bounds, m)
+    out = {"workload": DICT_WORKLOAD, "query_samples": len(w["query"]), "dict_segments": len(bounds) - 1,
+           "segment_samples": int(bounds[1] - bounds[0]), "m": m, "pairs_per_step": pairs, "tiers": {}}
+    results = {}
+    for tier in TIER_NAMES:
+        P = torch.empty(WA, dtype=torch.float32, device="cuda")
+        I = torch.empty(WA, dtype=torch.int64, device="cuda")
+        dt, kms, kpairs = time_join(abjoin, q, d, bounds, m, tier, steps, warmup, P, I)
+        out["tiers"][tier] = {"pairs_per_s": pairs / dt, "ms_per_step": dt * 1e3,
+                              "roofline": roofline(tier, m, DICT_WORKLOAD, kms, kpairs)}
+        results[tier] = (P.cpu().numpy(), I.cpu().numpy())
+    for tier in TIER_NAMES:
+        out["tiers"][tier]["vs_fp32"] = out["tiers"][tier]["pairs_per_s"] / out["tiers"]["fp32"]["pairs_per_s"]
+    log(f"dictionary workload fp32: {out['tiers']['fp32']['pairs_per_s']:.3e} pairs/s")
+    return out, (w, results)
 
 
-def pipeline_errors(record, check, threads, rows=256):
-    """The first held-out series against the FP64 oracle: its dictionary join
-    on `rows` random rows, and its discords' values (exact distances to the
-    whole database) at the rows returned."""
+def dictionary_errors(record, data, threads, rows=2048):
     import oracle
 
-    q, D, dbounds, ref, rbounds, m, Ph, Ih, found = check
+    w, results = data
+    q, d, b, m = w["query"], w["dict"], w["bounds"], w["m"]
     W = len(q) - m + 1
-    sample = np.sort(np.random.default_rng(77).choice(W, rows, replace=False))
-    Po, Io, P2o = oracle.ab_join(q, D, dbounds, m, rows=sample, threads=threads, second=True)
-    clear = (P2o - Po) > 1e-3
-    record["dictionary_join_vs_oracle"] = {
-        "rows": rows, "max_abs": float(np.abs(Ph[sample] - Po).max()),
-        "index_match_clear_rows": float(np.mean(Ih[sample][clear] == Io[clear])) if clear.any() else 1.0}
-    drows = np.asarray(found["rows"], dtype=np.int64)
-    Pd, _ = oracle.ab_join(q, ref, rbounds, m, rows=np.sort(drows), threads=threads)
-    order = np.argsort(drows)
-    got = np.asarray(found["values"], dtype=np.float64)[order]
-    record["discord_values_vs_oracle"] = {"rows": int(len(drows)), "max_abs": float(np.abs(got - Pd).max())}
-
-
-def time_tier(abjoin, q, d, bounds, m, tier, steps, warmup, P, I):
-    import torch
-
-    for _ in range(warmup):
-        abjoin.ab_join(q, d, bounds, m, tier=tier, out=(P, I))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        abjoin.ab_join(q, d, bounds, m, tier=tier, out=(P, I))
-    torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / steps
+    sample = np.sort(np.random.default_rng(54321).choice(W, rows, replace=False))
+    Po, Io, P2o = oracle.ab_join(q, d, b, m, rows=sample, threads=threads, second=True)
+    for tier, (P, I) in results.items():
+        record["tiers"][tier]["error_vs_oracle"] = error_stats(P[sample], I[sample], Po, Io, P2o)
 
 
 def serving(abjoin, synth, tiers, n_req: int, fracs=(0.5, 0.8, 0.95)):
@@ -279,24 +365,141 @@ def serving(abjoin, synth, tiers, n_req: int, fracs=(0.5, 0.8, 0.95)):
                                   "p99_ms": st["p99_s"] * 1e3, "max_ms": st["max_s"] * 1e3,
                                   "pairs_per_s": st["pairs"] / st["busy_s"], "batches": st["batches"]})
         out["tiers"][tier] = rec
+        log(f"serving {tier}: saturation {rec['saturation_pairs_per_s']:.3e} pairs/s, "
+            f"p99 at 50% load {rec['levels'][0]['p99_ms']:.2f} ms")
     dct.close()
     return out
+
+
+def pipeline(abjoin, synth, tier="bf16", n=262144, n_series=8, m=256, space_saving=0.9, K=50):
+    """The whole method at the size of the database workload: the learning
+    phase (Alg. 1) on each of n_series ECG-like database series, their
+    dictionaries concatenated into one resident dictionary, the n_series
+    held-out series (50 planted anomalous beats each) joined against it
+    through the serving loop in the given tier (Alg. 2), and their exact top-K
+    discords against the whole database from that join (Lemmas 1-2, with the
+    certification tests of Sec. 2).  e_max is the largest of the per-series
+    values, an upper bound for the concatenated dictionary.  Reports the time
+    of each phase and how many planted beats the discords hit (a discord
+    within one beat, 260 samples, of a planted start)."""
+    import torch
+
+    db = [synth.ecg_like(n, synth.rng_for(11, k)) for k in range(n_series)]
+    held = [synth.ecg_like(n, synth.rng_for(12, k), n_anomalies=50, return_anomalies=True) for k in range(n_series)]
+    db_dev = [torch.from_numpy(x).cuda() for x in db]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    learned = [abjoin.dict_build(x, m, stop="space_saving", value=space_saving) for x in db_dev]
+    torch.cuda.synchronize()
+    t_learn = time.perf_counter() - t0
+    D = torch.cat([g["dictionary"] for g in learned])
+    dbounds = [0]
+    for g in learned:
+        dbounds += [dbounds[-1] + int(b) for b in g["bounds"][1:]]
+    e_max = max(g["e_max"] for g in learned)
+    ref = torch.cat(db_dev)
+    rbounds = [k * n for k in range(n_series + 1)]
+    W = n - m + 1
+    V = valid_windows(dbounds, m)
+    # the inference phase through the serving loop: the dictionary resident,
+    # every held-out series submitted at once
+    dct = abjoin.Dictionary(D.cpu().numpy(), dbounds, (m,))
+    srv = abjoin.Server(dct, tier=tier, max_slots=n_series, mem_budget=8 << 30)
+    t0 = time.perf_counter()
+    ids = [srv.submit(x, m) for x, _ in held]
+    joined = [srv.result(i)[:2] if srv.wait(i, 600000) == abjoin.ABJ_OK else None for i in ids]
+    t_join = time.perf_counter() - t0
+    srv.close()
+    dct.close()
+    assert all(j is not None for j in joined)
+    held_dev = [torch.from_numpy(x).cuda() for x, _ in held]
+    t0 = time.perf_counter()
+    found = [abjoin.discords(q, torch.from_numpy(np.ascontiguousarray(Ph, dtype=np.float32)).cuda(), e_max, ref,
+                             rbounds, m, K) for q, (Ph, _) in zip(held_dev, joined)]
+    torch.cuda.synchronize()
+    t_disc = time.perf_counter() - t0
+    hits = 0
+    for (_, starts), r in zip(held, found):
+        for row in r["rows"]:
+            hits += int(np.any(np.abs(starts - int(row)) <= 260))
+    check = {"held": [x for x, _ in held], "db": np.concatenate(db), "rbounds": np.asarray(rbounds), "m": m,
+             "K": K, "e_max": e_max, "P_hat": [np.asarray(Ph, dtype=np.float64) for Ph, _ in joined],
+             "found": found, "D": D.cpu().numpy(), "dbounds": np.asarray(dbounds)}
+    log(f"pipeline: join {t_join * 1e3 / n_series:.1f} ms per series ({tier}, serving loop)")
+    return check, {
+        "database": f"{n_series} x {n} ECG-like", "held_out": f"{n_series} x {n}, 50 planted beats each",
+        "m": m, "space_saving": space_saving, "K": K, "tier": tier, "join_path": "serving loop (resident dictionary)",
+        "dictionary_samples": int(D.numel()), "dictionary_segments": len(dbounds) - 1, "e_max": e_max,
+        "learn_ms_per_series": t_learn * 1e3 / n_series,
+        "join_ms_per_series": t_join * 1e3 / n_series, "join_pairs_per_s": n_series * W * V / t_join,
+        "discords_ms_per_series": t_disc * 1e3 / n_series,
+        "exact_rows_fraction": float(np.mean([r["rows_exact"] / W for r in found])),
+        "rounds": [int(r["rounds"]) for r in found], "certified_bits": [int(r["certified"]) for r in found],
+        "discords_on_planted_beats": f"{hits} of {n_series * K}"}
+
+
+def pipeline_oracle(record, check, threads, series):
+    """Held-out series `series` against the FP64 streaming oracle over the
+    whole database (every row): the dictionary join's error E = P_hat - P
+    against e_max (Lemmas 1-2: 0 <= E <= e_max up to the join's tolerance),
+    and the exact top-K discord sets (positions within m/2, values)."""
+    import oracle
+    from oracle import discords as odisc
+
+    m, K, e_max = check["m"], check["K"], check["e_max"]
+    out = []
+    for k in series:
+        q = check["held"][k]
+        W = len(q) - m + 1
+        t0 = time.perf_counter()
+        parts = []
+        for r0 in range(0, W, 1 << 15):  # slices of 32,768 rows, one progress line each
+            r1 = min(W, r0 + (1 << 15))
+            parts.append(oracle.ab_join_stream(q[r0:r1 + m - 1], check["db"], check["rbounds"], m,
+                                               threads=threads)[0])
+            log(f"pipeline oracle series {k}: rows {r1} of {W}")
+        Po = np.concatenate(parts)
+        dt = time.perf_counter() - t0
+        E = check["P_hat"][k] - Po
+        fin = np.isfinite(E)
+        orows, ovals = odisc.topk_discords(Po, K, m - 1)
+        g = check["found"][k]
+        grows = np.asarray(g["rows"], dtype=np.int64)
+        matched = sum(int(np.any(np.abs(grows - r) <= m // 2)) for r in orows)
+        # values of the GPU's discords against the oracle profile at the same rows
+        vdiff = np.abs(np.asarray(g["values"], dtype=np.float64) - Po[grows]) if grows.size else np.zeros(0)
+        out.append({"series": int(k), "rows": int(len(Po)), "oracle_s": dt,
+                    "oracle_pairs_per_s": len(Po) * valid_windows(check["rbounds"], m) / dt,
+                    "E_mean": float(E[fin].mean()), "E_std": float(E[fin].std()), "E_max": float(E[fin].max()),
+                    "E_min": float(E[fin].min()), "E_max_le_e_max": bool(E[fin].max() <= e_max + TOL),
+                    "E_min_ge_minus_tol": bool(E[fin].min() >= -TOL),
+                    "discords_matched": f"{matched} of {len(orows)}",
+                    "discord_values_max_abs": float(vdiff.max()) if vdiff.size else 0.0,
+                    "oracle_certified_literal": odisc.top_certified(check["P_hat"][k], e_max),
+                    "oracle_certified_runner_up": odisc.top_certified(check["P_hat"][k], e_max, m - 1)})
+        log(f"pipeline oracle series {k}: {dt:.1f} s, discords {out[-1]['discords_matched']}")
+    record["vs_oracle_full_database"] = out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--tier", default="fp32", choices=["fp32"])
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-tiers", action="store_true", help="skip the BF16/FP16 comparison")
-    ap.add_argument("--no-serving", action="store_true", help="skip the serving workload")
-    ap.add_argument("--no-pipeline", action="store_true", help="skip the learning + join + discords pipeline")
-    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, "rw1m_m128"],
-                    help="the timed join: the dictionary workload (default) or 1M x 1M random walks at m = 128")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, DICT_WORKLOAD],
+                    help="the headline join: 1M x 1M random walks at m = 128 (default) or the dictionary workload")
+    ap.add_argument("--oracle-rows", type=int, default=4096, help="query rows of the oracle sample")
+    ap.add_argument("--no-cpu", action="store_true", help="skip every oracle leg")
+    ap.add_argument("--no-tiers", action="store_true", help="time the FP32 tier only")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the dictionary workload, the short windows, serving and the pipeline")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-pipeline", action="store_true")
+    ap.add_argument("--pipeline-oracle", default="one", choices=["none", "one", "all"],
+                    help="held-out series compared with the streaming oracle over the whole database")
     ap.add_argument("--serve-requests", type=int, default=4096)
+    ap.add_argument("--only", default=None, choices=list(TIER_NAMES),
+                    help="profiling: run only the timed steps of this tier on the headline workload")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="after the timed steps, run one device-to-device copy of this many bytes "
                          "(reference dispatch for scaling HBM counters)")
@@ -310,103 +513,76 @@ def main():
 
     from paper_2112_12965_amd import abjoin, synth
 
-    w = synth.WORKLOADS[args.workload]()
-    m, bounds = w["m"], w["bounds"]
-    q = torch.from_numpy(w["query"]).cuda()
-    d = torch.from_numpy(w["dict"]).cuda()
-    WA = len(w["query"]) - m + 1
-    V = valid_windows(bounds, m)
-    pairs = WA * V
-    P = torch.empty(WA, dtype=torch.float32, device="cuda")
-    I = torch.empty(WA, dtype=torch.int64, device="cuda")
-    L = abjoin.lib()
+    threads = max(1, min(16, host_cores()))
+    if args.only:
+        w = synth.WORKLOADS[args.workload]()
+        m, bounds = w["m"], w["bounds"]
+        q, d = torch.from_numpy(w["query"]).cuda(), torch.from_numpy(w["dict"]).cuda()
+        WA = len(w["query"]) - m + 1
+        P = torch.empty(WA, dtype=torch.float32, device="cuda")
+        I = torch.empty(WA, dtype=torch.int64, device="cuda")
+        dt, kms, kp = time_join(abjoin, q, d, bounds, m, args.only, args.steps, args.warmup, P, I)
+        if args.copy_bytes > 0:
+            src = torch.empty(args.copy_bytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+            torch.empty_like(src).copy_(src)
+            torch.cuda.synchronize()
+        print(json.dumps({"tier": args.only, "workload": args.workload, "ms_per_step": dt * 1e3, "kernel_ms": kms,
+                          "kernel_pairs": kp}), flush=True)
+        return
 
-    for _ in range(args.warmup):
-        abjoin.ab_join(q, d, bounds, m, tier=args.tier, out=(P, I))
-    torch.cuda.synchronize()
-    L.abj_profile_enable(1)
-    abjoin.lib().abj_profile_read(None, None, None)  # clear
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        abjoin.ab_join(q, d, bounds, m, tier=args.tier, out=(P, I))
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    import ctypes
-
-    kms, nl, kp = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64()
-    L.abj_profile_read(ctypes.byref(kms), ctypes.byref(nl), ctypes.byref(kp))
-    L.abj_profile_enable(0)
-    if args.copy_bytes > 0:
-        src = torch.empty(args.copy_bytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-    kernel_ms = kms.value / max(nl.value, 1)
-    kernel_pairs = kp.value / max(nl.value, 1)
-    achieved = FLOPS_PER_PAIR * kernel_pairs / (kernel_ms * 1e-3)
-    src = os.path.join(ROOT, "paper_2112_12965_amd", "csrc", "join_fp32.hip")
-
-    def prof(kind):
-        return os.path.join(ROOT, "profiles", f"k_join_fp32_{args.workload}_{kind}_counters.md")
-
+    w, pairs, tiers, results = headline(abjoin, synth, args)
+    w["name"] = args.workload
+    extra = {}
+    if not args.no_extra:
+        extra["dictionary_workload"], dict_data = (dictionary_workload(abjoin, synth, args.steps, args.warmup)
+                                                   if args.workload != DICT_WORKLOAD else (None, None))
+        extra["tiers_short_windows"], short_data = short_windows(abjoin, synth, (16, 32, 64), 1 << 20,
+                                                                 max(3, args.steps // 4))
+        if not args.no_pipeline:
+            pipe_check, extra["pipeline"] = pipeline(abjoin, synth)
+        if not args.no_serving:
+            extra["serving"] = serving(abjoin, synth, ("fp32", "bf16"), args.serve_requests)
+    cb = None
+    if not args.no_cpu:
+        log(f"oracle leg: {args.oracle_rows} rows, {threads} threads")
+        cb = oracle_leg(w, results, tiers, args.oracle_rows, threads)
+        if not args.no_extra:
+            if dict_data is not None:
+                dictionary_errors(extra["dictionary_workload"], dict_data, threads)
+            short_window_errors(extra["tiers_short_windows"], short_data, threads)
+            if not args.no_pipeline and args.pipeline_oracle != "none":
+                n_series = len(pipe_check["held"])
+                pipeline_oracle(extra["pipeline"], pipe_check, threads,
+                                range(n_series) if args.pipeline_oracle == "all" else (0,))
+    # the headline: the fastest tier within the stated bar (FP32 without the oracle leg)
+    best = "fp32"
+    if cb is not None:
+        for tier, rec in tiers.items():
+            if rec["error_vs_oracle"]["max_abs"] <= TOL and rec["pairs_per_s"] > tiers[best]["pairs_per_s"]:
+                best = tier
+    head = tiers[best]
+    m = w["m"]
     out = {
         "metric": METRIC,
-        "value": pairs * args.steps / dt,
+        "value": head["pairs_per_s"],
         "unit": "pair-distances/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": dt * 1e3 / args.steps,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": {"fp32": "f32", "bf16": "bf16", "fp16": "f16"}[best],
         "data": "synthetic",
-        "config": {"workload": args.workload, "query_samples": len(w["query"]), "dict_segments": len(bounds) - 1,
-                   "segment_samples": int(bounds[1] - bounds[0]), "m": m, "tier": args.tier,
-                   "pairs_per_step": pairs},
-        "roofline": {"bound": "alu", "kernel": "k_join_fp32", "achieved": achieved / 1e12,
-                     "peak": FP32_PEAK / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_PEAK, "flops_per_pair": FLOPS_PER_PAIR,
-                     "kernel_ms": kernel_ms,
-                     "traffic": profiled_field(src, prof("hbm"), "traffic_bytes_per_launch")},
+        "config": {"workload": args.workload, "query_samples": len(w["query"]),
+                   "dict_segments": len(w["bounds"]) - 1, "m": m, "tier": best, "pairs_per_step": pairs,
+                   "stated_error": f"|P - P_oracle| <= {TOL} after refinement, on {args.oracle_rows} sampled rows"},
+        "roofline": head["roofline"],
+        "cpu_baseline": cb,
+        "tiers": tiers,
     }
-    # the same kernel against the issue ceiling of its FMA-class instructions,
-    # with their lane-instructions per pair (FP64 edges included) from the
-    # committed counters; the other VALU instructions (maxima, selects, the DPP
-    # add) are listed too, but some of them issue faster than 16 lanes a clock
-    fpp = profiled_field(src, prof("valu_types"), "fma_class_lane_instructions_per_pair")
-    vpp = profiled_field(src, prof("valu_types"), "valu_lane_instructions_per_pair")
-    out["roofline"]["valu_issue"] = None if fpp is None else {
-        "fma_class_lane_instructions_per_pair": fpp, "all_valu_lane_instructions_per_pair": vpp,
-        "ceiling_lane_instructions_per_s": VALU_LANE_INSTR_PER_S,
-        "frac": kernel_pairs / (kernel_ms * 1e-3) * fpp / VALU_LANE_INSTR_PER_S}
-    results = {"fp32": (P.cpu().numpy(), I.cpu().numpy())}
-    if not args.no_tiers:
-        out["tiers"] = {"fp32": {"pairs_per_s": out["value"], "ms_per_step": out["ms_per_step"]}}
-        for tier in ("bf16", "fp16"):
-            Pt = torch.empty_like(P)
-            It = torch.empty_like(I)
-            dtt = time_tier(abjoin, q, d, bounds, m, tier, max(args.steps // 5, 3), 2, Pt, It)
-            out["tiers"][tier] = {"pairs_per_s": pairs / dtt, "ms_per_step": dtt * 1e3,
-                                  "vs_fp32": (pairs / dtt) / out["value"]}
-            results[tier] = (Pt.cpu().numpy(), It.cpu().numpy())
-        # the precision tier against the FP32 tier where its O(m) products are short
-        out["tiers_short_windows"], short_data = short_windows(abjoin, synth)
-    if not args.no_pipeline:
-        pipe_check, out["pipeline"] = pipeline(abjoin, synth)
-    if not args.no_cpu:
-        threads = min(16, os.cpu_count() or 1)
-        cb, errs = cpu_baseline(w, results, args.cpu_seconds, threads)
-        out["cpu_baseline"] = cb
-        out["error_vs_oracle"] = errs
-        if not args.no_tiers:
-            short_window_errors(out["tiers_short_windows"], short_data, threads)
-        if not args.no_pipeline:
-            pipeline_errors(out["pipeline"], pipe_check, threads)
-    if not args.no_serving:
-        out["serving"] = serving(abjoin, synth, ("fp32", "bf16"), args.serve_requests)
+    out.update({k: v for k, v in extra.items() if v is not None})
     print(json.dumps(out), flush=True)
 
 

@@ -160,14 +160,15 @@ def _bounds(seg_bounds):
 
 
 def ab_join(query, dictionary, seg_bounds: Sequence[int], m: int, tier: str = "fp32", refine_k: int = 0,
-            out: Optional[tuple] = None, stream=None, pearson: bool = False):
+            out: Optional[tuple] = None, stream=None, pearson: bool = False, no_refine: bool = False):
     """Matrix profile of ``query`` against the windows of a concatenated dictionary.
 
     ``query``/``dictionary``: float64 CUDA tensors; ``seg_bounds``: host int64
     offsets (``[0, len(dictionary)]`` for a plain AB-join).  Returns
     ``(P, I)``: float32 distances and int64 indices (CUDA tensors), enqueued on
     the current stream.  ``pearson``: P holds the correlation of the nearest
-    window instead of its distance.
+    window instead of its distance.  ``no_refine`` (16-bit tiers): skip the
+    FP64 re-check and report the distance implied by the best 16-bit score.
     """
     import torch
 
@@ -180,7 +181,8 @@ def ab_join(query, dictionary, seg_bounds: Sequence[int], m: int, tier: str = "f
         I = torch.empty(W, dtype=torch.int64, device=q.device)
     else:
         P, I = out
-    o = abj_opts(TIERS[tier], int(refine_k), ABJ_FLAG_PEARSON if pearson else 0, 0)
+    o = abj_opts(TIERS[tier], int(refine_k),
+                 (ABJ_FLAG_PEARSON if pearson else 0) | (ABJ_FLAG_NO_REFINE if no_refine else 0), 0)
     rc = lib().ab_join(q.data_ptr(), q.numel(), d.data_ptr(), d.numel(), bp, nseg, int(m),
                        P.data_ptr() if W else None, I.data_ptr() if W else None, ctypes.byref(o),
                        _stream_ptr(stream))

@@ -353,10 +353,18 @@ __device__ __forceinline__ void join_tile(const Fp32Slot& sl, int64_t band, int6
             if (i < WA) pc[i] = best[r] > -INFINITY ? pack_key(best[r], bidx[r]) : 0ull;
         }
     } else {
+        // the row key only grows, so a tile whose key does not beat the value
+        // read back needs no atomic: after the first tiles of a band most
+        // rows are already settled, and the atomics (each a read and write
+        // beyond the L2) drop from one per row and tile to about the number of
+        // improvements.  A stale read only costs an unneeded atomic.
 #pragma unroll
         for (int r = 0; r < kR; ++r) {
             const int64_t i = ibase + r;
-            if (i < WA && best[r] > -INFINITY) atomicMax(&keys[i], pack_key(best[r], bidx[r]));
+            if (i < WA && best[r] > -INFINITY) {
+                const unsigned long long k = pack_key(best[r], bidx[r]);
+                if (k > keys[i]) atomicMax(&keys[i], k);
+            }
         }
     }
 }

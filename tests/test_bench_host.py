@@ -41,11 +41,11 @@ def test_valid_windows_brute_force(seed):
     assert bench.valid_windows(bounds, m) == brute
 
 
-@pytest.mark.parametrize("workload", [bench.WORKLOAD, "rw1m_m128"])
+@pytest.mark.parametrize("workload", [bench.DICT_WORKLOAD, "rw1m_m128"])
 def test_committed_counters_match_the_kernel_source(workload):
     # the bench reports HBM traffic and the FMA-class issue fraction only while
     # the committed summaries were taken on the current kernel source
-    kinds = ["valu_types"] + (["hbm"] if workload == bench.WORKLOAD else [])
+    kinds = ["valu_types", "hbm"]
     for kind in kinds:
         summary = os.path.join(ROOT, "profiles", f"k_join_fp32_{workload}_{kind}_counters.md")
         text = open(summary).read()

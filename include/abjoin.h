@@ -212,10 +212,15 @@ typedef struct {
  *   e_max        host (out, may be NULL): e_max of the final dictionary
  *                (+inf if it is empty)
  *   p_self       device, n-m+1 doubles (out, may be NULL): P_B
+ * Sizing call: with segments, chosen and dict_out all NULL nothing runs and
+ * the call returns, in whichever of *n_segments, *n_chosen and *n_dict are
+ * given, upper bounds that every run with these n, m and opts respects
+ * (series may then be NULL): buffers of those sizes never fail the run.
  * Blocking: runs on hip_stream and synchronises it once per step.
  * Errors: ABJ_EINVAL for m outside [2, 4096], n < m, bad opts, NULL required
  * pointers or non-device buffers, and (after the run, with no output
- * written) when the segments or choices exceed max_segments / max_chosen;
+ * written) when the segments or choices exceed max_segments / max_chosen
+ * (buffers sized by the sizing call are always large enough);
  * ABJ_ENOMEM / ABJ_EHIP from the runtime.
  */
 int dict_build(const double* series, int64_t n, int32_t m, const abj_learn_opts* opts, int64_t* segments,
@@ -284,13 +289,27 @@ typedef struct abj_dict abj_dict;
 
 /*
  * dict: host or device pointer to n_dict doubles (copied; the caller keeps
- * ownership).  seg_bounds: host, n_seg+1 offsets.  ms: host, n_ms window
- * lengths (each 2..4096, n_ms 1..16).  Errors: ABJ_EINVAL on bad sizes, bounds
- * or pointers; ABJ_ENOMEM / ABJ_EHIP from the runtime.
+ * ownership).  seg_bounds: host, n_seg+1 offsets.  orig_start: host, n_seg
+ * entries or NULL: where each segment starts in the series it was taken from
+ * (dict_build's segments; Sec. 4.2 builds D_B from pieces of T_B), kept so
+ * that join results can be mapped back; NULL makes the dictionary its own
+ * source (orig_start[s] = seg_bounds[s]).  ms: host, n_ms window lengths (each
+ * 2..4096, n_ms 1..16).  Errors: ABJ_EINVAL on bad sizes, bounds, a negative
+ * orig_start or pointers; ABJ_ENOMEM / ABJ_EHIP from the runtime.
  */
-int abj_dict_create(const double* dict, int64_t n_dict, const int64_t* seg_bounds, int32_t n_seg, const int32_t* ms,
-                    int32_t n_ms, abj_dict** out);
+int abj_dict_create(const double* dict, int64_t n_dict, const int64_t* seg_bounds, int32_t n_seg,
+                    const int64_t* orig_start, const int32_t* ms, int32_t n_ms, abj_dict** out);
 int abj_dict_free(abj_dict* d);
+
+/*
+ * Maps n dictionary indices (I_AB of a join against d) to positions in the
+ * source series: out[i] = orig_start[s] + (I[i] - seg_bounds[s]) for the
+ * segment s holding I[i]; an index outside [0, n_dict) (the -1 of a row with
+ * no neighbour) maps to -1.  I and out are device buffers of n int64 (they
+ * may be the same buffer).  Asynchronous on hip_stream.  Errors: ABJ_EINVAL
+ * for a NULL dictionary, n < 0 or non-device buffers.
+ */
+int abj_dict_source_index(const abj_dict* d, const int64_t* I, int64_t n, int64_t* out, void* hip_stream);
 
 /* ab_join against a resident dictionary (m must be one of its ms).  Same
  * conventions, outputs and errors as ab_join; query, P_AB, I_AB are device

@@ -107,8 +107,9 @@ def lib():
                                ctypes.POINTER(_i32), ctypes.POINTER(abj_discord_info), _vp]
         L.abj_profile_enable.argtypes = [ctypes.c_int]
         L.abj_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
-        L.abj_dict_create.argtypes = [_vp, _i64, ctypes.POINTER(_i64), _i32, ctypes.POINTER(_i32), _i32,
-                                      ctypes.POINTER(_vp)]
+        L.abj_dict_create.argtypes = [_vp, _i64, ctypes.POINTER(_i64), _i32, ctypes.POINTER(_i64),
+                                      ctypes.POINTER(_i32), _i32, ctypes.POINTER(_vp)]
+        L.abj_dict_source_index.argtypes = [_vp, _vp, _i64, _vp, _vp]
         L.abj_dict_free.argtypes = [_vp]
         L.ab_join_dict.argtypes = [_vp, _vp, _i64, _i32, _vp, _vp, ctypes.POINTER(abj_opts), _vp]
         L.abj_server_create.argtypes = [_vp, ctypes.POINTER(abj_server_opts), ctypes.POINTER(_vp)]
@@ -122,7 +123,7 @@ def lib():
         L.abj_server_destroy.argtypes = [_vp]
         for f in ("abj_init", "abj_window_stats", "ab_join", "ab_join_noalloc", "self_join", "dict_build", "topk_discords", "discords",
                   "abj_profile_enable", "abj_profile_read",
-                  "abj_dict_create", "abj_dict_free", "ab_join_dict", "abj_server_create", "abj_submit",
+                  "abj_dict_create", "abj_dict_source_index", "abj_dict_free", "ab_join_dict", "abj_server_create", "abj_submit",
                   "abj_submit_borrowed", "abj_wait", "abj_result", "abj_cancel", "abj_server_drain",
                   "abj_server_stats_get", "abj_server_destroy"):
             getattr(L, f).restype = ctypes.c_int
@@ -222,16 +223,19 @@ def dict_build(series, m: int, context: float = 1.5, stop: str = "space_saving",
     x = _dev_f64(series, "series")
     n = x.numel()
     W = max(n - m + 1, 0)
-    cap = W if max_iters <= 0 else min(W, max_iters)
-    segs = np.zeros(2 * max(cap, 1), dtype=np.int64)
-    chosen = np.zeros(max(cap, 1), dtype=np.int64)
-    d = torch.empty(max(n, 1), dtype=torch.float64, device=x.device)
-    pb = torch.empty(max(W, 1), dtype=torch.float64, device=x.device)
     nseg, nch, nd, em = _i32(0), _i32(0), _i64(0), ctypes.c_double(0.0)
     o = abj_learn_opts(float(context), float(value), STOPS[stop], int(max_iters))
+    # sizing call: upper bounds on the segments, choices and dictionary length
+    _check(lib().dict_build(None, n, int(m), ctypes.byref(o), None, 0, ctypes.byref(nseg), None, 0,
+                            ctypes.byref(nch), None, ctypes.byref(nd), None, None, None))
+    max_seg, max_ch = max(nseg.value, 1), max(nch.value, 1)
+    segs = np.zeros(2 * max_seg, dtype=np.int64)
+    chosen = np.zeros(max_ch, dtype=np.int64)
+    d = torch.empty(max(nd.value, 1), dtype=torch.float64, device=x.device)
+    pb = torch.empty(max(W, 1), dtype=torch.float64, device=x.device)
     _check(lib().dict_build(x.data_ptr(), n, int(m), ctypes.byref(o), segs.ctypes.data_as(ctypes.POINTER(_i64)),
-                            max(cap, 1), ctypes.byref(nseg), chosen.ctypes.data_as(ctypes.POINTER(_i64)),
-                            max(cap, 1), ctypes.byref(nch), d.data_ptr(), ctypes.byref(nd), ctypes.byref(em),
+                            max_seg, ctypes.byref(nseg), chosen.ctypes.data_as(ctypes.POINTER(_i64)),
+                            max_ch, ctypes.byref(nch), d.data_ptr(), ctypes.byref(nd), ctypes.byref(em),
                             pb.data_ptr() if W else None, _stream_ptr(stream)))
     sg = [(int(segs[2 * k]), int(segs[2 * k + 1])) for k in range(nseg.value)]
     bounds = np.concatenate([[0], np.cumsum([b - a for a, b in sg])]).astype(np.int64)
@@ -303,7 +307,7 @@ class Dictionary:
     """A dictionary kept resident in device memory (library-owned), with window
     statistics precomputed for every window length in ``ms``."""
 
-    def __init__(self, dictionary, seg_bounds, ms):
+    def __init__(self, dictionary, seg_bounds, ms, orig_start=None):
         import torch
 
         if isinstance(dictionary, torch.Tensor):
@@ -314,8 +318,14 @@ class Dictionary:
             ptr, n, self._keep = x.ctypes.data, len(x), x
         b, bp, nseg = _bounds(seg_bounds)
         m_arr = (ctypes.c_int32 * len(ms))(*[int(v) for v in ms])
+        op = None
+        if orig_start is not None:
+            self._orig = np.ascontiguousarray(np.asarray(orig_start, dtype=np.int64))
+            if len(self._orig) != nseg:
+                raise ValueError("orig_start needs one entry per segment")
+            op = self._orig.ctypes.data_as(ctypes.POINTER(_i64))
         h = ctypes.c_void_p()
-        _check(lib().abj_dict_create(ptr, n, bp, nseg, m_arr, len(ms), ctypes.byref(h)))
+        _check(lib().abj_dict_create(ptr, n, bp, nseg, op, m_arr, len(ms), ctypes.byref(h)))
         self.handle = h
         self.ms = tuple(int(v) for v in ms)
         self.n = n
@@ -336,6 +346,19 @@ class Dictionary:
         _check(lib().ab_join_dict(self.handle, q.data_ptr(), q.numel(), int(m), P.data_ptr() if W else None,
                                   I.data_ptr() if W else None, ctypes.byref(o), _stream_ptr(stream)))
         return P, I
+
+    def source_index(self, I, out=None, stream=None):
+        """Positions in the source series of dictionary indices ``I`` (int64
+        CUDA tensor; -1 stays -1)."""
+        import torch
+
+        if not isinstance(I, torch.Tensor) or not I.is_cuda or I.dtype != torch.int64 or not I.is_contiguous():
+            raise TypeError("I must be a contiguous int64 CUDA tensor")
+        if out is None:
+            out = torch.empty_like(I)
+        _check(lib().abj_dict_source_index(self.handle, I.data_ptr() if I.numel() else None, I.numel(),
+                                           out.data_ptr() if I.numel() else None, _stream_ptr(stream)))
+        return out
 
     def close(self):
         if self.handle:

@@ -372,7 +372,14 @@ extern "C" int dict_build(const double* series, int64_t n, int32_t m, const abj_
                           double* p_self, void* hip_stream)
 {
     // ---- validation ----
-    ABJ_TRY(check_self_args(series, n, m, nullptr));
+    // sizing call: no segments, chosen or dict_out buffer; nothing runs
+    const bool sizing = !segments && !chosen && !dict_out;
+    if (sizing) {
+        if (m < 2 || m > kMaxM) return set_error(ABJ_EINVAL, "m must be in [2, %d] (got %d)", kMaxM, m);
+        if (n < m || n > kMaxN) return set_error(ABJ_EINVAL, "n must be in [m, 2^31-1] (got %lld)", (long long)n);
+    } else {
+        ABJ_TRY(check_self_args(series, n, m, nullptr));
+    }
     if (!opts) return set_error(ABJ_EINVAL, "opts is NULL");
     const abj_learn_opts o = *opts;
     if (!(o.context > 0.0) || !isfinite(o.context)) return set_error(ABJ_EINVAL, "context must be finite and > 0");
@@ -386,6 +393,22 @@ extern "C" int dict_build(const double* series, int64_t n, int32_t m, const abj_
         return set_error(ABJ_EINVAL, "unknown stop condition %d", o.stop);
     }
     if (o.max_iters < 0) return set_error(ABJ_EINVAL, "max_iters must be >= 0");
+    if (sizing) {
+        // upper bounds that hold for every run: chosen windows are more than
+        // m/2 (rounded down) apart, merged segments hold at least
+        // ceil(context m) samples (at least m, at most n) and do not touch
+        const int64_t W = n - m + 1;
+        const int64_t Lmin = std::max<int64_t>(m, std::min<int64_t>(n, (int64_t)ceil(o.context * (double)m)));
+        int64_t most_chosen = (W + m / 2) / (m / 2 + 1);
+        if (o.max_iters > 0) most_chosen = std::min<int64_t>(most_chosen, o.max_iters);
+        const int64_t most_segs = std::min<int64_t>(n / (Lmin + 1) + 1, most_chosen);
+        if (!n_segments && !n_chosen && !n_dict)
+            return set_error(ABJ_EINVAL, "a sizing call needs n_segments, n_chosen or n_dict");
+        if (n_segments) *n_segments = (int32_t)std::min<int64_t>(most_segs, INT32_MAX);
+        if (n_chosen) *n_chosen = (int32_t)std::min<int64_t>(most_chosen, INT32_MAX);
+        if (n_dict) *n_dict = n;
+        return ABJ_OK;
+    }
     if (!segments || !n_segments || max_segments < 0)
         return set_error(ABJ_EINVAL, "segments / n_segments are required");
     if (chosen && max_chosen < 0) return set_error(ABJ_EINVAL, "max_chosen must be >= 0");

@@ -53,9 +53,10 @@ struct abj_dict {
     int device = 0;
     int64_t n = 0;
     std::vector<int64_t> bounds;
-    std::vector<int64_t> orig_start;  // per segment: its first sample in the source series (empty: not given)
+    std::vector<int64_t> orig_start;  // per segment: its first sample in the source series
     double* x = nullptr;
     int64_t* dbounds = nullptr;
+    int64_t* dorig = nullptr;  // orig_start on the device
     std::vector<DictM> per_m;
     mutable std::mutex op_mu;  // guards the lazily built 16-bit dictionary sides
     const DictM* find(int32_t m) const
@@ -78,6 +79,7 @@ static void dict_release(abj_dict* d)
     }
     if (d->x) (void)hipFree(d->x);
     if (d->dbounds) (void)hipFree(d->dbounds);
+    if (d->dorig) (void)hipFree(d->dorig);
     delete d;
 }
 
@@ -123,12 +125,16 @@ int dict_operand(const abj_dict* d, const DictM* e, int tier, hipStream_t stream
 }  // namespace
 
 extern "C" int abj_dict_create(const double* dict, int64_t n_dict, const int64_t* seg_bounds, int32_t n_seg,
-                               const int32_t* ms, int32_t n_ms, abj_dict** out)
+                               const int64_t* orig_start, const int32_t* ms, int32_t n_ms, abj_dict** out)
 {
     if (!out) return set_error(ABJ_EINVAL, "out is NULL");
     if (!dict) return set_error(ABJ_EINVAL, "dict is NULL");
     if (n_dict < 1 || n_dict > kMaxN) return set_error(ABJ_EINVAL, "n_dict out of range");
     ABJ_TRY(check_bounds(seg_bounds, n_seg, n_dict));
+    if (orig_start)
+        for (int32_t s = 0; s < n_seg; ++s)
+            if (orig_start[s] < 0 || orig_start[s] > (int64_t(1) << 62))
+                return set_error(ABJ_EINVAL, "orig_start[%d] = %lld out of range", s, (long long)orig_start[s]);
     if (!ms || n_ms < 1 || n_ms > 16) return set_error(ABJ_EINVAL, "n_ms must be in 1..16");
     for (int32_t a = 0; a < n_ms; ++a) {
         if (ms[a] < 2 || ms[a] > kMaxM) return set_error(ABJ_EINVAL, "window length %d out of range", ms[a]);
@@ -147,17 +153,24 @@ extern "C" int abj_dict_create(const double* dict, int64_t n_dict, const int64_t
     ABJ_HIP(hipGetDevice(&d->device));
     d->n = n_dict;
     d->bounds.assign(seg_bounds, seg_bounds + n_seg + 1);
+    if (orig_start)
+        d->orig_start.assign(orig_start, orig_start + n_seg);
+    else
+        d->orig_start.assign(seg_bounds, seg_bounds + n_seg);  // the dictionary is its own source
     int rc = ABJ_OK;
     hipStream_t st = nullptr;
     do {
         if (hipMalloc(&d->x, sizeof(double) * (size_t)n_dict) != hipSuccess ||
-            hipMalloc(&d->dbounds, sizeof(int64_t) * (size_t)(n_seg + 1)) != hipSuccess) {
+            hipMalloc(&d->dbounds, sizeof(int64_t) * (size_t)(n_seg + 1)) != hipSuccess ||
+            hipMalloc(&d->dorig, sizeof(int64_t) * (size_t)n_seg) != hipSuccess) {
             rc = set_error(ABJ_ENOMEM, "dictionary allocation failed");
             break;
         }
         if (hipMemcpy(d->x, dict, sizeof(double) * (size_t)n_dict,
                       on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(d->dbounds, seg_bounds, sizeof(int64_t) * (size_t)(n_seg + 1), hipMemcpyHostToDevice) !=
+                hipSuccess ||
+            hipMemcpy(d->dorig, d->orig_start.data(), sizeof(int64_t) * (size_t)n_seg, hipMemcpyHostToDevice) !=
                 hipSuccess) {
             rc = set_error(ABJ_EHIP, "dictionary copy failed");
             break;
@@ -194,6 +207,48 @@ extern "C" int abj_dict_create(const double* dict, int64_t n_dict, const int64_t
         return rc;
     }
     *out = d;
+    return ABJ_OK;
+}
+
+namespace {
+// One lane per index: the segment holding I[i] by binary search over the
+// dictionary's offsets, then the same offset from that segment's source start.
+__global__ void k_source_index(const int64_t* __restrict__ I, int64_t n, const int64_t* __restrict__ bounds,
+                               const int64_t* __restrict__ orig, int32_t n_seg, int64_t n_dict,
+                               int64_t* __restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t v = I[i];
+    if (v < 0 || v >= n_dict) {
+        out[i] = -1;
+        return;
+    }
+    int32_t lo = 0, hi = n_seg - 1;  // last segment whose start is <= v
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (bounds[mid] <= v)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    out[i] = orig[lo] + (v - bounds[lo]);
+}
+}  // namespace
+
+extern "C" int abj_dict_source_index(const abj_dict* d, const int64_t* I, int64_t n, int64_t* out,
+                                     void* hip_stream)
+{
+    if (!d) return set_error(ABJ_EINVAL, "dictionary is NULL");
+    if (n < 0 || n > kMaxN) return set_error(ABJ_EINVAL, "n out of range");
+    if (n == 0) return ABJ_OK;
+    ABJ_TRY(check_dev_buf(I, sizeof(int64_t) * (size_t)n, "I"));
+    ABJ_TRY(check_dev_buf(out, sizeof(int64_t) * (size_t)n, "out"));
+    ABJ_TRY(ensure_device());
+    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+    const int32_t n_seg = (int32_t)d->bounds.size() - 1;
+    k_source_index<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(I, n, d->dbounds, d->dorig, n_seg, d->n, out);
+    ABJ_HIP(hipGetLastError());
     return ABJ_OK;
 }
 

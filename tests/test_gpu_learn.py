@@ -188,3 +188,35 @@ def test_dict_build_rejects_bad_options():
         with pytest.raises(abjoin.AbjError) as e:
             abjoin.dict_build(x, 64, **kw)
         assert e.value.code == abjoin.ABJ_EINVAL
+
+
+def test_dict_build_sized_buffers_and_source_index():
+    # a run to exhaustion fits the buffers the sizing call asked for, and the
+    # resident dictionary maps join results back to the training series
+    T = training_series(3000, 12)
+    m = 32
+    print(f"[case] dict_build exhaustion n={len(T)} m={m}", flush=True)
+    g = gpu_build(T, m, stop="space_saving", value=0.0)
+    assert len(g["chosen"]) > 10
+    replay(T, m, g, stop="space_saving", value=0.0)
+    d = abjoin.Dictionary(dev(g["dictionary"]), g["bounds"], [m], orig_start=g["orig_start"])
+    plain = abjoin.Dictionary(dev(g["dictionary"]), g["bounds"], [m])
+    try:
+        q = training_series(4000, 13)
+        P, I = d.join(dev(q), m)
+        src = d.source_index(I)
+        same = plain.source_index(I)
+        torch.cuda.synchronize()
+        I, src, same = I.cpu().numpy(), src.cpu().numpy(), same.cpu().numpy()
+        assert np.array_equal(same, I)
+        ok = I >= 0
+        assert ok.all()
+        s = np.searchsorted(g["bounds"], I, side="right") - 1
+        assert np.array_equal(src, g["orig_start"][s] + I - g["bounds"][s])
+        for i in np.flatnonzero(ok)[:: max(1, ok.sum() // 200)]:
+            assert np.array_equal(T[src[i]:src[i] + m], g["dictionary"][I[i]:I[i] + m])
+        neg = torch.tensor([-1, len(g["dictionary"]), 0], dtype=torch.int64, device="cuda")
+        assert d.source_index(neg).cpu().tolist() == [-1, -1, int(g["orig_start"][0])]
+    finally:
+        d.close()
+        plain.close()

@@ -357,15 +357,31 @@ def serving(abjoin, synth, tiers, n_req: int, fracs=(0.5, 0.8, 0.95)):
 
         sat = run(None)
         sat_qps = sat["completed"] / sat["busy_s"]
+        # the same request set joined one at a time through the resident
+        # dictionary (one stream, one request per call), for comparison
+        import torch
+
+        sched = synth.serving_schedule(n_req, 1e9, synth.rng_for(4, 0))
+        offs = synth.rng_for(4, 99).integers(0, len(pool) - 65536, n_req)
+        qs = [torch.from_numpy(pool[offs[k]:offs[k] + r.length]).cuda() for k, r in enumerate(sched)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for q, r in zip(qs, sched):
+            dct.join(q, r.m, tier=tier)
+        torch.cuda.synchronize()
+        one_s = time.perf_counter() - t0
+        del qs
         rec = {"saturation_pairs_per_s": sat["pairs"] / sat["busy_s"], "saturation_qps": sat_qps,
-               "batches": sat["batches"], "levels": []}
+               "batches": sat["batches"], "one_shot_pairs_per_s": sat["pairs"] / one_s,
+               "served_vs_one_shot": (sat["pairs"] / sat["busy_s"]) / (sat["pairs"] / one_s), "levels": []}
         for f in fracs:
             st = run(f * sat_qps)
             rec["levels"].append({"qps": f * sat_qps, "load": f, "p50_ms": st["p50_s"] * 1e3,
                                   "p99_ms": st["p99_s"] * 1e3, "max_ms": st["max_s"] * 1e3,
                                   "pairs_per_s": st["pairs"] / st["busy_s"], "batches": st["batches"]})
         out["tiers"][tier] = rec
-        log(f"serving {tier}: saturation {rec['saturation_pairs_per_s']:.3e} pairs/s, "
+        log(f"serving {tier}: saturation {rec['saturation_pairs_per_s']:.3e} pairs/s "
+            f"({rec['served_vs_one_shot']:.2f}x one request at a time), "
             f"p99 at 50% load {rec['levels'][0]['p99_ms']:.2f} ms")
     dct.close()
     return out

@@ -171,6 +171,40 @@ __device__ inline void topk_insert(float (&tv)[K], int (&ti)[K], float v, int j)
         }
 }
 
+// The same for a lane's own sweep, where the scores are stamped (below) and a
+// later equal score comes from a later block, hence a larger index: the
+// value alone decides.
+template <int K>
+__device__ inline void topk_insert_stamped(float (&tv)[K], int (&ti)[K], float v, int j)
+{
+    if (!(v > tv[K - 1])) return;
+#pragma unroll
+    for (int q = K - 1; q >= 1; --q) {
+        const bool shift = v > tv[q - 1];  // v goes at or before q - 1
+        const bool here = !shift && v > tv[q];
+        tv[q] = shift ? tv[q - 1] : here ? v : tv[q];
+        ti[q] = shift ? ti[q - 1] : here ? j : ti[q];
+    }
+    if (v > tv[0]) {
+        tv[0] = v;
+        ti[0] = j;
+    }
+}
+
+// A score below every real one: the top-K lists start with it and masked
+// windows take it (finite, so that stamping keeps it a number).
+constexpr float kNoScore = -3.0e38f;
+
+// Stamps accumulator v's position into the low 4 bits of its score (15 - v,
+// so that equal scores rank the smaller row first): the scores of a lane's
+// block become distinct and the largest carries its own position.  It moves a
+// score by at most 15 units in the last place, far below the 16-bit inputs'
+// resolution.
+__device__ inline float stamp(float x, int v)
+{
+    return __uint_as_float((__float_as_uint(x) & ~15u) | (unsigned)(15 - v));
+}
+
 // Largest of 16 values (NaN-free inputs; the compiler forms max3 chains).
 __device__ inline float max16(const float (&a)[16])
 {
@@ -239,7 +273,7 @@ __global__ __launch_bounds__(kWave* NW) __attribute__((amdgpu_waves_per_eu(WPE))
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
         for (int q = 0; q < KH; ++q) {
-            tv[nb][q] = -INFINITY;
+            tv[nb][q] = kNoScore;
             ti[nb][q] = -1;
         }
 
@@ -319,32 +353,32 @@ __global__ __launch_bounds__(kWave* NW) __attribute__((amdgpu_waves_per_eu(WPE))
                         // insert the lane's values above its KH-th best, the
                         // largest first (at most KH of them can stay); in a
                         // block that straddles a segment break (rare) the
-                        // masked windows are removed first
+                        // masked windows are removed first.  Stamped scores
+                        // give each pass its position without a search.
                         asm volatile("" ::: "memory");
                         float a[16];
 #pragma unroll
-                        for (int v = 0; v < 16; ++v) a[v] = acc[h][nb][v];
+                        for (int v = 0; v < 16; ++v) a[v] = stamp(acc[h][nb][v], v);
                         if (partial) {
                             uint32_t mm = __builtin_amdgcn_readfirstlane(msk[h]);
                             asm volatile("" : "+s"(mm));  // keeps the per-lane tests inside the branch
 #pragma unroll
                             for (int v = 0; v < 16; ++v)
-                                if (!((mm >> acc_row(v, lane)) & 1u)) a[v] = -INFINITY;
-                            mx = max16(a);
-                            hit = mx > tv[nb][KH - 1];
+                                if (!((mm >> acc_row(v, lane)) & 1u)) a[v] = kNoScore;
                         }
-#pragma unroll
+                        mx = max16(a);
+                        hit = mx > tv[nb][KH - 1];
+                        constexpr int kPassUnroll = KH <= 4 ? KH : 1;  // a rolled loop for 8 keeps the registers
+#pragma unroll kPassUnroll
                         for (int pass = 0; pass < KH; ++pass) {
                             if (__builtin_amdgcn_ballot_w64(hit) == 0) break;
                             if (hit) {
-                                // first (smallest row) position of the lane's largest value
-                                int sel = 15;
-#pragma unroll
-                                for (int v = 14; v >= 0; --v) sel = a[v] == mx ? v : sel;
-                                topk_insert<KH>(tv[nb], ti[nb], mx, jbase + acc_row(sel, lane));
+                                const int sel = 15 - (int)(__float_as_uint(mx) & 15u);
+                                topk_insert_stamped<KH>(tv[nb], ti[nb], mx, jbase + acc_row(sel, lane));
                                 if (pass + 1 < KH) {
+                                    // the next largest: everything below this one
 #pragma unroll
-                                    for (int v = 0; v < 16; ++v) a[v] = v == sel ? -INFINITY : a[v];
+                                    for (int v = 0; v < 16; ++v) a[v] = a[v] < mx ? a[v] : kNoScore;
                                     mx = max16(a);
                                     hit = mx > tv[nb][KH - 1];
                                 }
@@ -690,10 +724,13 @@ int mfma_plan(int64_t WA, int64_t WB, int32_t m, int tier, int refine_k, MfmaPla
     p->ndblk = (WB + 31) / 32;
     const int64_t qblk_per_panel = (int64_t)NW * NB;
     p->npanels = (p->nqblk + qblk_per_panel - 1) / qblk_per_panel;
-    // split the dictionary sweep until there are enough workgroups to fill the
-    // chip, but keep at least 64 blocks (2,048 windows) per chunk
+    // split the dictionary sweep until the workgroups fill the chip once (512
+    // workgroups of 4-8 waves: 4 waves per SIMD), but keep at least 64 blocks
+    // (2,048 windows) per chunk: a shorter sweep spends more of its blocks
+    // before its top-K thresholds settle, when nearly every block takes the
+    // insert path
     int64_t nchunks = 1;
-    while (p->npanels * nchunks < 2048 && (p->ndblk + nchunks * 2 - 1) / (nchunks * 2) >= 64) nchunks *= 2;
+    while (p->npanels * nchunks < 512 && (p->ndblk + nchunks * 2 - 1) / (nchunks * 2) >= 64) nchunks *= 2;
     while (nchunks * K > 512) nchunks /= 2;  // the re-check reads at most 512 candidates per row
     // a reference shorter than m has no block: one empty chunk (no sweep)
     p->blk_per_chunk = p->ndblk > 0 ? (p->ndblk + nchunks - 1) / nchunks : 1;

@@ -420,14 +420,18 @@ constexpr int kFinRows = 4;  // query rows (one wave each) per workgroup of the 
 
 // One wave per query row.  The row's candidates from every chunk are taken
 // best-first, each dropping the others within kRefineRadius of it, up to
-// `keep` picks.  Then every lane computes one FP64 distance in full, for a
-// window near a pick: with L = 64 / (keep rounded up to a power of two) lanes
-// per pick, lane l takes pick l / L shifted by (l % L) - L/2 + 1 (for 4 picks,
-// the windows from 7 before to 8 after each); windows outside the reference
-// or that cannot match are skipped.  One wave-wide argmin (ties: smaller
-// index) gives the row's result.  With `refine` off, report the distance
-// implied by the best 16-bit score instead.  Flat / non-finite conventions as
-// in the FP32 tier.
+// `keep` picks.  Then the windows near the picks are re-checked in FP64: with
+// L = 64 / (keep rounded up to a power of two) lanes per pick, pick p covers
+// the L windows from L/2 - 1 before it to L/2 after it (for 4 picks, 7 before
+// to 8 after).  A lane takes 4 consecutive windows of its pick and a quarter
+// of the samples: a sliding window of 4 reference samples gives 4 FP64 FMAs
+// per sample pair, and the quarters are summed across lanes.  The distance
+// comes from the covariance, sum (a - mu_a) b (the centred row sums to zero,
+// so the reference's mean drops out), as sqrt(2m (1 - rho)).  Windows outside
+// the reference or that cannot match are skipped.  One wave-wide argmin (ties:
+// smaller index) gives the row's result.  With `refine` off, report the
+// distance implied by the best 16-bit score instead.  Flat / non-finite
+// conventions as in the FP32 tier.
 __global__ __launch_bounds__(kWave* kFinRows) void k_finalize_topk(MfmaFinJob one, const MfmaFinJob* __restrict__ jobs,
                                                                   int njobs)
 {
@@ -507,36 +511,80 @@ __global__ __launch_bounds__(kWave* kFinRows) void k_finalize_topk(MfmaFinJob on
         }
         if (J.refine && npick > 0) {
             const int L = J.keep <= 1 ? 64 : J.keep <= 2 ? 32 : J.keep <= 4 ? 16 : 8;
-            const int pr = lane / L;
+            const int pr = lane / L, g = lane % L;
+            const int Q = L / 4;          // lanes per sample quarter
+            const int kq = g / Q;         // this lane's quarter of the samples
+            const int sg = g % Q;         // this lane's 4 windows: 4 sg .. 4 sg + 3 of the pick's L
             int64_t base = -1;
 #pragma unroll
             for (int r = 0; r < kMaxPicks; ++r)
                 if (r == pr) base = pick[r];
-            const int64_t t = base + (lane % L) - L / 2 + 1;
-            double dd = INFINITY;
-            if (base >= 0 && t >= 0 && t < J.WB && bflags[t] == 0) {
+            const int64_t t0 = base - L / 2 + 1 + 4 * sg;  // first window of the lane
+            const int mq = (m + 3) / 4;
+            const int k0 = kq * mq, k1 = k0 + mq < m ? k0 + mq : m;
+            double cv[4] = {0.0, 0.0, 0.0, 0.0};
+            if (base >= 0) {
                 const auto xa = gptr(J.axc + i);
-                const auto xb = gptr(J.bxc + t);
-                const double ma = gptr(J.amu)[i], ia = 1.0 / gptr(J.asig)[i];
-                const double mb = gptr(J.bmu)[t], ib = 1.0 / gptr(J.bsig)[t];
-                // four independent sums keep several loads in flight
-                double acc[4] = {0.0, 0.0, 0.0, 0.0};
-                int k = 0;
-                for (; k + 4 <= m; k += 4) {
+                const auto xb = gptr(J.bxc);
+                const double ma = gptr(J.amu)[i];
+                // the window's samples t0 + r + k; below 0 only for windows
+                // that are skipped, so those loads are clamped to 0
+                auto bat = [&](int64_t x) { return xb[x > 0 ? x : 0]; };
+                double w0 = bat(t0 + k0), w1 = bat(t0 + k0 + 1), w2 = bat(t0 + k0 + 2);
+                int k = k0;
+                for (; k + 4 <= k1; k += 4) {
+                    double av[4], bv[4];
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
-                        const double e = (xa[k + u] - ma) * ia - (xb[k + u] - mb) * ib;
-                        acc[u] = fma(e, e, acc[u]);
+                        av[u] = xa[k + u] - ma;
+                        bv[u] = bat(t0 + k + u + 3);
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        cv[0] = fma(av[u], w0, cv[0]);
+                        cv[1] = fma(av[u], w1, cv[1]);
+                        cv[2] = fma(av[u], w2, cv[2]);
+                        cv[3] = fma(av[u], bv[u], cv[3]);
+                        w0 = w1;
+                        w1 = w2;
+                        w2 = bv[u];
                     }
                 }
-                for (; k < m; ++k) {
-                    const double e = (xa[k] - ma) * ia - (xb[k] - mb) * ib;
-                    acc[0] = fma(e, e, acc[0]);
+                for (; k < k1; ++k) {
+                    const double av = xa[k] - ma, bv = bat(t0 + k + 3);
+                    cv[0] = fma(av, w0, cv[0]);
+                    cv[1] = fma(av, w1, cv[1]);
+                    cv[2] = fma(av, w2, cv[2]);
+                    cv[3] = fma(av, bv, cv[3]);
+                    w0 = w1;
+                    w1 = w2;
+                    w2 = bv;
                 }
-                dd = sqrt((acc[0] + acc[1]) + (acc[2] + acc[3]));
+            }
+            // the four quarters' sums (lanes Q and 2Q apart within the pick)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                cv[r] += __shfl_xor(cv[r], Q, kWave);
+                cv[r] += __shfl_xor(cv[r], 2 * Q, kWave);
+            }
+            double dd = INFINITY;
+            int64_t tt = INT64_MAX;
+            if (base >= 0 && kq == 0) {
+                const double sa = gptr(J.asig)[i];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t t = t0 + r;
+                    if (t >= 0 && t < J.WB && bflags[t] == 0) {
+                        const double rho = cv[r] / ((double)m * sa * gptr(J.bsig)[t]);
+                        const double dt = sqrt(fmax(0.0, 2.0 * (double)m * (1.0 - rho)));
+                        if (dt < dd) {  // windows in increasing order: ties keep the smaller
+                            dd = dt;
+                            tt = t;
+                        }
+                    }
+                }
             }
             // wave argmin of (distance, window); lanes without a window hold +inf
-            int64_t tt = dd < INFINITY ? t : INT64_MAX;
 #pragma unroll
             for (int off = 32; off >= 1; off >>= 1) {
                 const double od = __shfl_xor(dd, off, kWave);

@@ -269,13 +269,20 @@ __global__ __launch_bounds__(kWave* NW) __attribute__((amdgpu_waves_per_eu(WPE))
     }
     float tv[NB][KH];
     int ti[NB][KH];
+    // gate: the larger of the two lane halves' KH-th best scores (lanes l and
+    // l ^ 32 hold the same query window).  The row's merged top KH is never
+    // below it, so a score below it can be skipped; exchanged after every
+    // insert.
+    float gate[NB];
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
+    for (int nb = 0; nb < NB; ++nb) {
+        gate[nb] = kNoScore;
 #pragma unroll
         for (int q = 0; q < KH; ++q) {
             tv[nb][q] = kNoScore;
             ti[nb][q] = -1;
         }
+    }
 
     // stage s holds dictionary blocks db_lo + s G .. + G - 1, fragment order
     // (block, ks, lane) exactly as in global memory, so the copy is linear;
@@ -348,7 +355,7 @@ __global__ __launch_bounds__(kWave* NW) __attribute__((amdgpu_waves_per_eu(WPE))
                         for (int v = 0; v < 16; ++v) c[v] = acc[h][nb][v];
                         mx = max16(c);
                     }
-                    bool hit = mx > tv[nb][KH - 1];
+                    bool hit = mx > gate[nb];
                     if (__builtin_expect(__builtin_amdgcn_ballot_w64(hit) != 0 || partial, 0)) {
                         // insert the lane's values above its KH-th best, the
                         // largest first (at most KH of them can stay); in a
@@ -367,7 +374,7 @@ __global__ __launch_bounds__(kWave* NW) __attribute__((amdgpu_waves_per_eu(WPE))
                                 if (!((mm >> acc_row(v, lane)) & 1u)) a[v] = kNoScore;
                         }
                         mx = max16(a);
-                        hit = mx > tv[nb][KH - 1];
+                        hit = mx > gate[nb];
                         constexpr int kPassUnroll = KH <= 4 ? KH : 1;  // a rolled loop for 8 keeps the registers
 #pragma unroll kPassUnroll
                         for (int pass = 0; pass < KH; ++pass) {
@@ -380,10 +387,12 @@ __global__ __launch_bounds__(kWave* NW) __attribute__((amdgpu_waves_per_eu(WPE))
 #pragma unroll
                                     for (int v = 0; v < 16; ++v) a[v] = a[v] < mx ? a[v] : kNoScore;
                                     mx = max16(a);
-                                    hit = mx > tv[nb][KH - 1];
+                                    hit = mx > fmaxf(gate[nb], tv[nb][KH - 1]);
                                 }
                             }
                         }
+                        const float own = tv[nb][KH - 1];
+                        gate[nb] = fmaxf(own, __shfl_xor(own, 32, kWave));
                     }
                 }
             }

@@ -224,11 +224,20 @@ extern "C" int discords(const double* query, int64_t n_query, int32_t m, const f
     ABJ_TRY(read_keys(pk, 2, &hk, stream));
     if (hk[0] && e_max >= 0.0 && (!hk[1] || (double)key_value(hk[1]) < (double)top - e_max)) cert |= 2;
 
-    // ---- round 0: every row that can hold the top discord, and rows with no bound ----
+    // ---- round 0: the rows whose bound reaches the K-th greedy pick on P_hat
+    // (the loop's first step), and of those only the ones that can hold the
+    // top discord when e_max says so (Lemma 2: the top discord's exact value is
+    // at least top - e_max).  Rows with no bound (+inf) are always taken.  The
+    // loop below makes the result exact whatever this round takes. ----
     {
-        float thr = INFINITY;  // +inf rows (no dictionary window) always need the exact join
-        if (hk[0] && e_max >= 0.0) thr = (float)((double)top - e_max);
-        // rounding the threshold down keeps every row with P_hat >= top - e_max
+        std::vector<unsigned long long> first;
+        ABJ_TRY(greedy(P_hat, W, K, excl, dead, pk, stream));
+        ABJ_TRY(read_keys(pk, K, &first, stream));
+        float thr = INFINITY;
+        for (int32_t k = 0; k < K && first[k]; ++k) thr = key_value(first[k]);  // the last (lowest) pick
+        if (!first[0]) thr = INFINITY;
+        if (hk[0] && e_max >= 0.0) thr = std::max(thr, (float)((double)top - e_max));
+        // rounding the threshold down keeps every row at or above it
         if (isfinite(thr)) thr = nextafterf(thr, -INFINITY);
         hipLaunchKernelGGL(k_mark_bands, dim3(grid_of(W)), dim3(kBlock), 0, stream, P_hat, W, thr, bflag);
         ABJ_HIP(hipGetLastError());

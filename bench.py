@@ -599,6 +599,11 @@ def main():
         "tiers": tiers,
     }
     out.update({k: v for k, v in extra.items() if v is not None})
+    if extra.get("serving"):
+        # the metric's latency part: the serving workload's p50 / p99 at each load
+        out["latency_ms"] = {
+            tier: {f"load_{lv['load']:.2f}": {"p50": lv["p50_ms"], "p99": lv["p99_ms"]} for lv in rec["levels"]}
+            for tier, rec in extra["serving"]["tiers"].items()}
     print(json.dumps(out), flush=True)
 
 

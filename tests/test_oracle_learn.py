@@ -116,3 +116,41 @@ def test_element_of_matches_hand_derived_golden():
         a, b = got
         # structural facts that hold for every case: the window is inside its element
         assert a <= c["j"] and c["j"] + c["m"] <= b and 0 <= a and b <= c["n"]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_merge_elements_is_the_union_of_the_intervals(seed):
+    """Alg. 1's merge: the segments cover exactly the union of the elements,
+    sorted, and no two of them overlap or touch (reading 10)."""
+    rng = np.random.default_rng(seed)
+    n = 300
+    els = []
+    for _ in range(int(rng.integers(1, 12))):
+        a = int(rng.integers(0, n - 5))
+        els.append((a, int(min(n, a + rng.integers(1, 40)))))
+    segs = learn.merge_elements(els)
+    cover = np.zeros(n + 1, dtype=bool)
+    for a, b in els:
+        cover[a:b] = True
+    got = np.zeros(n + 1, dtype=bool)
+    for a, b in segs:
+        assert a < b and not got[a:b].any()
+        got[a:b] = True
+    assert np.array_equal(got, cover)
+    assert all(b1 < a2 for (_, b1), (a2, _) in zip(segs, segs[1:]))  # gaps between segments, in order
+
+
+def test_e_max_of_matches_brute_force():
+    """Def. 10 by plain loops: the largest, over the windows of T, of the
+    distance to the nearest window that lies inside one dictionary segment."""
+    rng = np.random.default_rng(8)
+    m = 6
+    T = np.cumsum(rng.standard_normal(90))
+    segs = [(3, 20), (40, 47), (60, 88)]
+
+    def z(w):
+        return (w - w.mean()) / w.std()
+
+    dwin = [T[j:j + m] for a, b in segs for j in range(a, b - m + 1)]
+    best = [min(np.sqrt(np.sum((z(T[i:i + m]) - z(v)) ** 2)) for v in dwin) for i in range(len(T) - m + 1)]
+    assert abs(learn.e_max_of(T, segs, m) - max(best)) < 1e-9

@@ -115,9 +115,10 @@ int abj_window_stats(const double* x, int64_t n, int32_t m, double* mu, double* 
  *   seg_bounds  host, n_seg+1 int64 offsets (see conventions)
  *   P_AB    device, n_query-m+1 floats (out)  I_AB  device, n_query-m+1 int64 (out)
  *   opts    NULL = FP32 tier
- * FP32 tier: m <= 4096; its error bound against FP64 (|P| within 1e-3) is
- * tested for m = 2 and m >= 8 (for m = 3..7 nearest distances can fall below
- * the resolution of FP32 pair scores).  BF16 / FP16 tiers (the paper's join with 16-bit
+ * FP32 tier: 2 <= m <= 4096, |P| within 1e-3 of FP64 (windows shorter than 8
+ * samples, whose nearest distances fall below the resolution of FP32 pair
+ * scores, compare FP64 correlations and run at about a fifth of the rate; the bar
+ * is tested for every m).  BF16 / FP16 tiers (the paper's join with 16-bit
  * window products, a speed/accuracy option of this library): m <= 256; every
  * row takes up to refine_k candidates best-first by 16-bit score (pairwise
  * more than 4 windows apart) and returns the closest window in FP64 among the

@@ -123,6 +123,12 @@ int stats_launch_many(const void* jobs_dev, int njobs, int64_t blk_sum, int64_t 
 // of this share the engine's tiling of the whole series.
 constexpr int64_t kFp32BandRows = 1024;
 
+// Windows shorter than this take the FP32 engine's exact path: every pair's
+// correlation from an FP64 dot product instead of the FP32 recurrence, whose
+// absolute error is too coarse for the tiny distances of very short windows,
+// and a row key that names the best column itself rather than its group.
+constexpr int kFp32SmallM = 8;
+
 // A view of rows [r0, r0 + rows) of the query statistics A, for joining or
 // finishing a subset of bands (the copy behind xc keeps its zero tail).  r0
 // is a multiple of 16 (the callers pass band starts), so that the 16-row copy
@@ -148,6 +154,7 @@ inline SeriesDev rows_view(const SeriesDev& A, int64_t r0, int64_t rows)
 struct Fp32Slot {
     const double* axc;
     const double* amu;
+    const double* asig;
     const float2* adfdg;
     int64_t WA;
     const double* bxc;

@@ -237,7 +237,8 @@ __device__ __forceinline__ void finalize_body(
     // ---- second round trip: the candidates' statistics and the groups'
     // spans ----
     const int64_t j = jb + c;
-    const bool cand = jb >= 0 && j < WB && (excl < 0 || j - i > excl || i - j > excl);
+    // windows shorter than kFp32SmallM: the key names the best column itself
+    const bool cand = jb >= 0 && j < WB && (excl < 0 || j - i > excl || i - j > excl) && (m >= kFp32SmallM || c == 0);
     const int64_t jc = cand ? j : 0;
     const uint8_t fj = cand ? bflags[jc] : (uint8_t)1;
     const double mbj = bmu[jc], sbj = bsig[jc];

@@ -369,6 +369,86 @@ __device__ __forceinline__ void join_tile(const Fp32Slot& sl, int64_t band, int6
     }
 }
 
+// Windows shorter than kFp32SmallM: one tile by FP64 dot products.  Lane l
+// keeps its 16 rows two at a time, each as the window minus its mean (at most
+// 7 samples, zero-padded); the columns stream through scalar loads of their 7
+// samples and weight (1/sigma, NaN when the window cannot match), so the
+// score sum_k (a_k - mu_a) b_k / sigma_b = m sigma_a rho needs no reference
+// mean (the centred row sums to zero).  The row key carries rho in 32-bit
+// fixed point (resolution 2^-31) and the column itself, not its group.
+typedef const __attribute__((address_space(4))) double* CDbl;
+constexpr int kSmallPad = kFp32SmallM - 1;  // samples per window register set
+
+__device__ inline unsigned long long small_key(double rho, int64_t j)
+{
+    const double r = rho < -1.0 ? -1.0 : rho > 1.0 ? 1.0 : rho;
+    const double f = (r + 1.0) * 2147483648.0;  // [0, 2^32]
+    const unsigned hi = f >= 4294967295.0 ? 0xFFFFFFFFu : (unsigned)f;
+    return ((unsigned long long)hi << 32) | (unsigned long long)(0xFFFFFFFFu - (unsigned)j);
+}
+
+template <bool kExcl>
+__device__ __forceinline__ void small_m_tile(const Fp32Slot& sl, int64_t band, int64_t chunk)
+{
+    GDbl __restrict__ axc = (GDbl)sl.axc;
+    GDbl __restrict__ amu = (GDbl)sl.amu;
+    GDbl __restrict__ asig = (GDbl)sl.asig;
+    CDbl __restrict__ bxc = (CDbl)sl.bxc;
+    ColPtr __restrict__ bcol = (ColPtr)sl.bcol;
+    const int64_t WA = sl.WA;
+    const int m = sl.m;
+    const int lane = threadIdx.x;
+    const int32_t __attribute__((address_space(4)))* ch = (const int32_t __attribute__((address_space(4)))*)sl.chunks;
+    const int64_t j0 = ch[2 * chunk], jend = ch[2 * chunk + 1];
+    const int64_t ibase = band * kBandRows + (int64_t)lane * kR;
+#pragma unroll 1
+    for (int r0 = 0; r0 < kR; r0 += 2) {
+        double za[2][kSmallPad], best[2] = {-INFINITY, -INFINITY};
+        int64_t bj[2] = {-1, -1};
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int64_t i = ibase + r0 + r;
+            const int64_t ic = i < WA ? i : WA - 1;
+            const double mu = amu[ic];
+#pragma unroll
+            for (int k = 0; k < kSmallPad; ++k) za[r][k] = k < m ? axc[ic + k] - mu : 0.0;
+        }
+        for (int64_t j = j0; j < jend; ++j) {
+            const float w = bcol[j][2];
+            double b[kSmallPad];
+#pragma unroll
+            for (int k = 0; k < kSmallPad; ++k) b[k] = bxc[j + k];  // < n + 6: the zero tail
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                double s = 0.0;
+#pragma unroll
+                for (int k = 0; k < kSmallPad; ++k) s = fma(za[r][k], b[k], s);
+                double sc = s * (double)w;  // NaN for a window that cannot match
+                if (kExcl) {
+                    const int64_t d = j - (ibase + r0 + r);
+                    if (d <= sl.excl && d >= -sl.excl) sc = -INFINITY;
+                }
+                if (sc > best[r]) {  // ties keep the smaller column
+                    best[r] = sc;
+                    bj[r] = j;
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int64_t i = ibase + r0 + r;
+            if (i >= WA) continue;
+            const double rho = bj[r] >= 0 ? best[r] / ((double)m * asig[i]) : NAN;
+            const unsigned long long k = rho >= -2.0 && rho <= 2.0 ? small_key(rho, bj[r]) : 0ull;
+            if (sl.part) {
+                sl.part[chunk * WA + i] = k;
+            } else if (k && k > sl.keys[i]) {
+                atomicMax(&sl.keys[i], k);
+            }
+        }
+    }
+}
+
 // Persistent batch kernel: workgroup w (one wave) first joins tile w, then
 // takes tiles from one of kTileQueues interleaved queues of the rest (queue q
 // holds tiles grid + q + kTileQueues k; its counter sits on a line of its
@@ -403,10 +483,15 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void
             // does the tile meet the band |j - i| <= excl?
             const int64_t i0 = band * kBandRows, i1 = i0 + kBandRows - 1;
             const int64_t j0 = sl.chunks[2 * chunk], j1 = sl.chunks[2 * chunk + 1] - 1;
-            if (sl.excl >= 0 && j0 - i1 <= sl.excl && j1 - i0 >= -sl.excl)
+            const bool zone = sl.excl >= 0 && j0 - i1 <= sl.excl && j1 - i0 >= -sl.excl;
+            if (sl.m < kFp32SmallM)
+                small_m_tile<true>(sl, band, chunk);
+            else if (zone)
                 join_tile<true>(sl, band, chunk, lds);
             else
                 join_tile<false>(sl, band, chunk, lds);
+        } else if (sl.m < kFp32SmallM) {
+            small_m_tile<false>(sl, band, chunk);
         } else {
             join_tile<false>(sl, band, chunk, lds);
         }
@@ -453,6 +538,7 @@ void fp32_slot(const SeriesDev& A, const SeriesDev& B, unsigned long long* keys,
 {
     sl->axc = A.xc;
     sl->amu = A.mu;
+    sl->asig = A.sig;
     sl->adfdg = A.dfdg;
     sl->WA = A.W;
     sl->bxc = B.xc;

@@ -224,3 +224,19 @@ def test_ecg_long_window(orc):
     src = synth.ecg_like(30000, synth.rng_for(92, 1))
     d, bounds, _ = synth.cut_dictionary(src, 4, 3000, synth.rng_for(92, 2))
     full_check(orc, q, d, bounds, 1000)
+
+
+@pytest.mark.parametrize("m", [3, 4, 5, 6, 7])
+@pytest.mark.parametrize("kind", ["noise", "rw"])
+def test_short_windows_exact_path(orc, m, kind):
+    # windows shorter than 8 samples: FP64 correlations pick the column, so
+    # the bar holds although nearest distances fall far below 1e-3
+    rng = np.random.default_rng(700 + m)
+    gen = (lambda n: rng.standard_normal(n)) if kind == "noise" else (lambda n: synth.random_walk(n, rng))
+    q = gen(5000)
+    d = gen(4000)
+    bounds = [0, 1500, 1503, 2600, 4000]  # a segment shorter than some m
+    full_check(orc, q, d, bounds, m)
+    # a query longer than one 1,024-row band and a reference of several chunks
+    q2, d2 = gen(3100), gen(2300)
+    full_check(orc, q2, d2, [0, len(d2)], m)

@@ -65,7 +65,7 @@ def check_self(orc, x, m, excl, exact_second=False):
     return float(err.max()) if err.size else 0.0
 
 
-@pytest.mark.parametrize("m,excl", [(2, -1), (16, -1), (16, 0), (100, -1), (64, 700)])
+@pytest.mark.parametrize("m,excl", [(2, -1), (3, -1), (5, 0), (7, -1), (16, -1), (16, 0), (100, -1), (64, 700)])
 def test_self_join_random_walk_exact(orc, m, excl):
     x = synth.random_walk(2600, np.random.default_rng(40 + m))
     check_self(orc, x, m, excl, exact_second=True)

@@ -126,3 +126,28 @@ def test_serving_workload_sample_equals_alone(served_dict):
             Pa, Ia = alone(d, qs[k], sched[k].m, "fp32")
             assert np.array_equal(P, Pa) and np.array_equal(I, Ia), k
     srv.close()
+
+
+def test_short_windows_served_and_resident(orc):
+    # the FP32 engine's exact path for windows shorter than 8 samples, through
+    # the resident dictionary and a serving batch that mixes it with m = 64
+    rng = np.random.default_rng(21)
+    dct = rng.standard_normal(3000)
+    bounds = [0, 1000, 2200, 3000]
+    d = abjoin.Dictionary(dct, bounds, (3, 64))
+    try:
+        reqs = [(rng.standard_normal(int(rng.integers(800, 4000))), (3, 64)[k % 2]) for k in range(6)]
+        print("[case] short windows served", flush=True)
+        srv = abjoin.Server(d, tier="fp32", max_slots=8)
+        ids = [srv.submit(q, m) for q, m in reqs]
+        for (q, m), i in zip(reqs, ids):
+            assert srv.wait(i, 60000) == abjoin.ABJ_OK
+            P, I, _ = srv.result(i)
+            Pa, Ia = alone(d, q, m, "fp32")
+            assert np.array_equal(P, Pa) and np.array_equal(I, Ia)
+            if m == 3:
+                Po, Io, P2o = orc.ab_join(q, dct, bounds, m, second=True)
+                _parity.compare(P, I, Po, Io, P2o, 1e-3, orc, q, dct, m, bounds)
+        srv.close()
+    finally:
+        d.close()

@@ -59,3 +59,14 @@ def test_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+@pytest.mark.parametrize("tier", ["bf16", "fp16"])
+@pytest.mark.parametrize("workload", [bench.DICT_WORKLOAD, "rw1m_m128"])
+def test_committed_matrix_core_counters_match_the_kernel_source(tier, workload):
+    src = os.path.join(ROOT, "paper_2112_12965_amd", "csrc", "join_mfma.hip")
+    for kind, field in (("hbm", "traffic_bytes_per_launch"), ("mfma", "mfma_busy_frac")):
+        summary = bench.summary_path(tier, workload, kind)
+        assert "rocprofv3 " in open(summary).read()
+        v = bench.profiled_field(src, summary, field)
+        assert v is not None and v > 0, f"{summary} was taken on another version of {src}: profile again"

@@ -50,6 +50,7 @@ constexpr int kQ = kTC / kWave;         // top-edge columns per lane
 static_assert(kR == 16 && kQ == 16, "the edge dot products read the 16-row copies: lanes 16 samples apart");
 constexpr int kDppWaveShr1 = 0x138;     // DPP control: whole-wave shift right by one lane
 constexpr int kG = 16;                  // width of the FP64 edge dot-product groups
+constexpr int64_t kGroupBands = 64;     // row bands per group of the tile order
 
 // The slot's arrays live in global memory; saying so keeps their loads global
 // (not flat) although the pointers come from a descriptor in memory.
@@ -477,8 +478,24 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void
         }
         const Fp32Slot sl = slots[lo];
         const int64_t lt = (int64_t)t - sl.tile0;
-        const int64_t band = lt / sl.nchunks;
-        const int64_t chunk = lt - band * sl.nchunks;
+        // a slot with more tiles than the grid runs its tiles in groups of
+        // kGroupBands row bands: a group walks the chunks in order with all of
+        // its bands per chunk, so the tiles in flight at once (a few thousand)
+        // cover a block of bands x chunks whose series data stays in the
+        // caches, instead of a few bands against every chunk (1M x 1M: 3.2x
+        // less fetched from beyond the L2s).  A slot that fits in one round
+        // keeps the plain band-major order, which measured 4% faster there.
+        int64_t band, chunk;
+        if (sl.nbands * sl.nchunks > (int64_t)grid) {
+            const int64_t g = lt / (kGroupBands * sl.nchunks);
+            const int64_t in = lt - g * kGroupBands * sl.nchunks;
+            const int64_t nb = sl.nbands - g * kGroupBands < kGroupBands ? sl.nbands - g * kGroupBands : kGroupBands;
+            chunk = in / nb;
+            band = g * kGroupBands + (in - chunk * nb);
+        } else {
+            band = lt / sl.nchunks;
+            chunk = lt - band * sl.nchunks;
+        }
         if (kSelf) {
             // does the tile meet the band |j - i| <= excl?
             const int64_t i0 = band * kBandRows, i1 = i0 + kBandRows - 1;

@@ -122,7 +122,9 @@ int abj_window_stats(const double* x, int64_t n, int32_t m, double* mu, double* 
  * window products, a speed/accuracy option of this library): m <= 256; every
  * row takes up to refine_k candidates best-first by 16-bit score (pairwise
  * more than 4 windows apart) and returns the closest window in FP64 among the
- * windows near a candidate (for refine_k <= 4: from 7 before to 8 after it).
+ * windows near a candidate (for refine_k <= 4: from 7 before to 8 after it);
+ * the 1e-3 bar is tested for m >= 8 (shorter windows have near-equal 16-bit
+ * scores by the hundred: use the FP32 tier there).
  * Errors: ABJ_EINVAL if m < 2 (or above the tier's limit), n_query < m,
  * n_dict < 1, n_seg < 1, bad seg_bounds, an unknown tier, refine_k outside
  * 0..8, unknown flag bits, nonzero reserved field, or a NULL / non-device

@@ -11,7 +11,9 @@
 // FP32 dots convert as they read, and a window of up to 256 samples then
 // takes its FP64 distance from the same stage, so a wave makes two memory
 // round trips: the keys with the row windows, then the groups' spans.  The
-// exchanges within a row run on the DPP path rather than through LDS.
+// exchanges within a row run on the DPP path rather than through LDS.  For
+// windows shorter than kFp32SmallM the key names the best column itself (the
+// tile kernel compared FP64 correlations), and only its distance is computed.
 #include <math.h>
 #include <string.h>
 

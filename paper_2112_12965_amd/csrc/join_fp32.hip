@@ -26,8 +26,11 @@
 //   * scores are folded with a max per row within each group of 16 columns and
 //     only the group is recorded, so the sweep has no data-dependent branch;
 //   * at the end each row's best (score, group) is merged across tiles with a
-//     64-bit atomic max on an order-preserving key (ties -> first group), and
-//     the epilogue picks the row's column within the group in FP64.
+//     64-bit atomic max on an order-preserving key (ties -> first group), or
+//     stored per chunk and reduced in the epilogue, which picks the row's
+//     column within the group;
+//   * windows shorter than kFp32SmallM take an exact path instead (FP64 dot
+//     products per pair, small_m_tile below).
 #include <math.h>
 #include <string.h>
 

@@ -317,6 +317,7 @@ struct MfmaBatchLaunch {
     std::vector<Group> groups;  // one sweep launch per (k steps, candidates)
     std::vector<int> empty;     // items whose dictionary has no window
     int64_t op_blocks = 0, fin_blocks = 0;
+    int max_keep = 0;           // the largest re-check pick count of the items (sizes the re-check's stage)
     size_t off_join = 0, off_fin = 0;
 };
 // Device bytes of the job tables of n items.

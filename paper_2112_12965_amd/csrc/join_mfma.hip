@@ -425,29 +425,104 @@ __global__ __launch_bounds__(kWave* NW) __attribute__((amdgpu_waves_per_eu(WPE))
 
 constexpr unsigned long long kNone = ~0ull;
 
-constexpr int kFinRows = 4;  // query rows (one wave each) per workgroup of the re-check
+constexpr int kFinRows = 2;  // query rows (one wave each) per workgroup of the re-check
+
+// Exchanges within a row of 16 lanes on the DPP path: quad_perm xor 1 and
+// xor 2, half-row mirror (xor 7), row rotate by 4 and by 8.
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppRor4 = 0x124, kDppRor8 = 0x128;
+template <int kCtrl>
+__device__ __forceinline__ unsigned dpp_u32(unsigned v)
+{
+    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, kCtrl, 0xf, 0xf, true);
+}
+template <int kCtrl>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long v)
+{
+    return ((unsigned long long)dpp_u32<kCtrl>((unsigned)(v >> 32)) << 32) | dpp_u32<kCtrl>((unsigned)v);
+}
+template <int kCtrl>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    return __longlong_as_double((long long)dpp_u64<kCtrl>((unsigned long long)__double_as_longlong(v)));
+}
+__device__ __forceinline__ unsigned long long lane_u64(unsigned long long v, int l)
+{
+    // readlane returns int: take both halves as unsigned before widening
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((unsigned)v, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((unsigned)(v >> 32), l);
+    return ((unsigned long long)hi << 32) | lo;
+}
+// The largest key of the wave (of its first 16 lanes if kRows is 1), wave-
+// uniform: each row of 16 lanes on the DPP path, then the rows' results
+// through scalar reads.
+template <int kRows>
+__device__ inline unsigned long long wave_max_u64(unsigned long long v)
+{
+    unsigned long long o = dpp_u64<kDppXor1>(v);
+    v = o > v ? o : v;
+    o = dpp_u64<kDppXor2>(v);
+    v = o > v ? o : v;
+    o = dpp_u64<kDppHalfMirror>(v);
+    v = o > v ? o : v;
+    o = dpp_u64<kDppRor8>(v);
+    v = o > v ? o : v;
+    unsigned long long w = lane_u64(v, 0);
+#pragma unroll
+    for (int r = 16; r < 16 * kRows; r += 16) {
+        const unsigned long long x = lane_u64(v, r);
+        w = x > w ? x : w;
+    }
+    return w;
+}
+// One argmin step over (distance, window): the partner's pair if it ranks
+// first (smaller distance, then smaller window).
+template <int kCtrl>
+__device__ __forceinline__ void argmin_step(double& d, int64_t& t)
+{
+    const double od = dpp_f64<kCtrl>(d);
+    const int64_t ot = (int64_t)dpp_u64<kCtrl>((unsigned long long)t);
+    if (od < d || (od == d && ot < t)) {
+        d = od;
+        t = ot;
+    }
+}
 
 // One wave per query row.  The row's candidates from every chunk are taken
 // best-first, each dropping the others within kRefineRadius of it, up to
 // `keep` picks.  Then the windows near the picks are re-checked in FP64: with
 // L = 64 / (keep rounded up to a power of two) lanes per pick, pick p covers
 // the L windows from L/2 - 1 before it to L/2 after it (for 4 picks, 7 before
-// to 8 after).  A lane takes 4 consecutive windows of its pick and a quarter
+// to 8 after).  The row's window minus its mean and each pick's span of
+// reference samples are staged in LDS, the spans two picks at a time (one
+// memory round trip each); the statistics of the windows are fetched while
+// the sums run.  A lane takes 4 consecutive windows of its pick and a quarter
 // of the samples: a sliding window of 4 reference samples gives 4 FP64 FMAs
-// per sample pair, and the quarters are summed across lanes.  The distance
-// comes from the covariance, sum (a - mu_a) b (the centred row sums to zero,
-// so the reference's mean drops out), as sqrt(2m (1 - rho)).  Windows outside
-// the reference or that cannot match are skipped.  One wave-wide argmin (ties:
-// smaller index) gives the row's result.  With `refine` off, report the
-// distance implied by the best 16-bit score instead.  Flat / non-finite
-// conventions as in the FP32 tier.
-__global__ __launch_bounds__(kWave* kFinRows) void k_finalize_topk(MfmaFinJob one, const MfmaFinJob* __restrict__ jobs,
-                                                                  int njobs)
+// per sample pair, and the quarters are summed across lanes, after which
+// each of the four lanes sharing the 4 windows finishes one of them.  The
+// distance comes from the covariance, sum (a - mu_a) b (the centred row sums
+// to zero, so the reference's mean drops out), as sqrt(2m (1 - rho)).
+// Windows outside the reference or that cannot match are skipped.  One
+// wave-wide argmin (ties: smaller index) gives the row's result.  Maxima and
+// minima across lanes take the DPP path within rows of 16 lanes and scalar
+// reads across rows.  With `refine` off, report the distance implied by the
+// best 16-bit score instead.  Flat / non-finite conventions as in the FP32
+// tier.  kMaxPick: the largest `keep` of the launch's jobs (4 or 8), which
+// sizes the stage (10.5 or 18.4 KiB per wave).
+template <int kMaxPick>
+__global__ __launch_bounds__(kWave* kFinRows) __attribute__((amdgpu_waves_per_eu(4))) void k_finalize_topk(
+    MfmaFinJob one, const MfmaFinJob* __restrict__ jobs, int njobs)
 {
+    // per wave: the row (256 doubles), then kMaxPick spans of up to
+    // m + 64 / kMaxPick - 1 reference samples (one pick of 64 lanes: m + 63)
+    constexpr int kSpanLen = kMaxPick <= 4 ? 256 + 15 : 256 + 7;
+    constexpr int kStage = 256 + (kMaxPick * kSpanLen > 256 + 63 ? kMaxPick * kSpanLen : 256 + 63);
+    __shared__ double stage_all[kFinRows][kStage];
     const MfmaFinJob J = jobs ? jobs[find_job(jobs, njobs, blockIdx.x)] : one;
     const int lane = threadIdx.x % kWave;
     const int64_t i = ((int64_t)blockIdx.x - J.blk0) * kFinRows + threadIdx.x / kWave;
     if (i >= J.WA) return;
+    double* __restrict__ sa = stage_all[threadIdx.x / kWave];
+    double* __restrict__ sb = sa + 256;
     const int m = J.m;
     const auto aflags = gptr(J.aflags);
     const auto bflags = gptr(J.bflags);
@@ -482,24 +557,31 @@ __global__ __launch_bounds__(kWave* kFinRows) void k_finalize_topk(MfmaFinJob on
 #pragma unroll
         for (int q = 0; q < kMaxPerLane; ++q) {
             const int t = lane + q * kWave;
-            mine[q] = t < J.ncand ? c[t] : 0ull;
+            mine[q] = 0ull;
+            if (q * kWave < J.ncand && t < J.ncand) mine[q] = c[t];  // first test uniform
         }
-        constexpr int kMaxPicks = 8;
-        int64_t pick[kMaxPicks];
+        // the row minus its mean, staged while the picks are taken
+        const double ma = gptr(J.amu)[i];
+        {
+            const auto xa = gptr(J.axc + i);
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                const int t = lane + x * kWave;
+                if (t < m) sa[t] = xa[t] - ma;
+            }
+        }
+        int64_t pick[kMaxPick];
+#pragma unroll
+        for (int r = 0; r < kMaxPick; ++r) pick[r] = -1;
         int npick = 0;
 #pragma unroll
-        for (int r = 0; r < kMaxPicks; ++r) {
-            pick[r] = -1;
+        for (int r = 0; r < kMaxPick; ++r) {
             if (r >= J.keep) continue;
-            unsigned long long lbest = 0ull;
+            unsigned long long lbest = mine[0];
 #pragma unroll
-            for (int q = 0; q < kMaxPerLane; ++q) lbest = mine[q] > lbest ? mine[q] : lbest;
-            unsigned long long wbest = lbest;
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) {
-                const unsigned long long o = __shfl_xor(wbest, off, kWave);
-                wbest = o > wbest ? o : wbest;
-            }
+            for (int q = 1; q < kMaxPerLane; ++q)
+                if (q * kWave < J.ncand) lbest = mine[q] > lbest ? mine[q] : lbest;  // uniform guard
+            const unsigned long long wbest = J.ncand <= 16 ? wave_max_u64<1>(lbest) : wave_max_u64<4>(lbest);
             if (wbest == 0ull) break;  // uniform
             const int64_t jj = (int64_t)(0xFFFFFFFFu - (unsigned)(wbest & 0xFFFFFFFFull));
             if (!J.refine) {
@@ -513,54 +595,102 @@ __global__ __launch_bounds__(kWave* kFinRows) void k_finalize_topk(MfmaFinJob on
             // re-check below covers them
 #pragma unroll
             for (int q = 0; q < kMaxPerLane; ++q) {
-                if (mine[q] == 0ull) continue;
+                if (q * kWave >= J.ncand) break;  // uniform
                 const int64_t jq = (int64_t)(0xFFFFFFFFu - (unsigned)(mine[q] & 0xFFFFFFFFull));
                 if (jq - jj <= kRefineRadius && jj - jq <= kRefineRadius) mine[q] = 0ull;
             }
         }
         if (J.refine && npick > 0) {
             const int L = J.keep <= 1 ? 64 : J.keep <= 2 ? 32 : J.keep <= 4 ? 16 : 8;
+            const int span = m + L - 1;  // reference samples of a pick's L windows, at most 256 + 63
+            // each pick's span, two picks' loads in flight at a time (samples
+            // below 0 belong to windows that are skipped: their loads are
+            // clamped to 0)
+            const auto xb = gptr(J.bxc);
+            constexpr int kSpanIt = (256 + 63 + kWave - 1) / kWave;
+#pragma unroll
+            for (int r0 = 0; r0 < kMaxPick; r0 += 2) {
+                if (r0 >= npick) break;  // uniform
+                double v[2][kSpanIt];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    // s0 >= -L/2 >= -32: only the first load can fall below 0
+                    const int64_t s0 = pick[r0 + h] - L / 2 + 1;
+                    const int64_t x0 = s0 + lane;
+                    v[h][0] = xb[x0 > 0 ? x0 : 0];
+                    const auto xu = xb + (x0 + kWave);
+#pragma unroll
+                    for (int u = 1; u < kSpanIt; ++u) v[h][u] = xu[(u - 1) * kWave];
+                }
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int u = 0; u < kSpanIt; ++u) {
+                        const int t = lane + u * kWave;
+                        if (r0 + h < npick && t < span) sb[(r0 + h) * span + t] = v[h][u];
+                    }
+            }
             const int pr = lane / L, g = lane % L;
             const int Q = L / 4;          // lanes per sample quarter
             const int kq = g / Q;         // this lane's quarter of the samples
             const int sg = g % Q;         // this lane's 4 windows: 4 sg .. 4 sg + 3 of the pick's L
             int64_t base = -1;
 #pragma unroll
-            for (int r = 0; r < kMaxPicks; ++r)
-                if (r == pr) base = pick[r];
+            for (int r = 0; r < kMaxPick; ++r)
+                if (r == pr && r < npick) base = pick[r];
             const int64_t t0 = base - L / 2 + 1 + 4 * sg;  // first window of the lane
-            const int mq = (m + 3) / 4;
+            // after the sums below, the four lanes of a window group (one per
+            // quarter) hold the same four sums: lane kq finishes window t0 + kq.
+            // Its statistics are fetched before the sums (a window outside the
+            // reference is skipped)
+            const int64_t tw = t0 + kq;
+            const bool fin = base >= 0 && tw >= 0 && tw < J.WB;
+            uint8_t wfl = 1;
+            double wsig = 1.0;
+            if (fin) {
+                wfl = bflags[tw];
+                wsig = gptr(J.bsig)[tw];
+            }
+            const double sa_ = gptr(J.asig)[i];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // an odd quarter length puts the quarters' samples on different
+            // LDS banks
+            const int mq = ((m + 3) / 4) | 1;
             const int k0 = kq * mq, k1 = k0 + mq < m ? k0 + mq : m;
             double cv[4] = {0.0, 0.0, 0.0, 0.0};
-            if (base >= 0) {
-                const auto xa = gptr(J.axc + i);
-                const auto xb = gptr(J.bxc);
-                const double ma = gptr(J.amu)[i];
-                // the window's samples t0 + r + k; below 0 only for windows
-                // that are skipped, so those loads are clamped to 0
-                auto bat = [&](int64_t x) { return xb[x > 0 ? x : 0]; };
-                double w0 = bat(t0 + k0), w1 = bat(t0 + k0 + 1), w2 = bat(t0 + k0 + 2);
+            if (base >= 0 && k0 < k1) {
+                const double* __restrict__ bw = sb + pr * span + 4 * sg;  // window t0 + r, sample k: bw[r + k]
+                double w0 = bw[k0], w1 = bw[k0 + 1], w2 = bw[k0 + 2];
                 int k = k0;
+#pragma unroll 2
                 for (; k + 4 <= k1; k += 4) {
-                    double av[4], bv[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        av[u] = xa[k + u] - ma;
-                        bv[u] = bat(t0 + k + u + 3);
-                    }
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        cv[0] = fma(av[u], w0, cv[0]);
-                        cv[1] = fma(av[u], w1, cv[1]);
-                        cv[2] = fma(av[u], w2, cv[2]);
-                        cv[3] = fma(av[u], bv[u], cv[3]);
-                        w0 = w1;
-                        w1 = w2;
-                        w2 = bv[u];
-                    }
+                    const double a0 = sa[k], a1 = sa[k + 1], a2 = sa[k + 2], a3 = sa[k + 3];
+                    const double b3 = bw[k + 3], b4 = bw[k + 4], b5 = bw[k + 5], b6 = bw[k + 6];
+                    // sample by sample, as the one-step loop below
+                    cv[0] = fma(a0, w0, cv[0]);
+                    cv[1] = fma(a0, w1, cv[1]);
+                    cv[2] = fma(a0, w2, cv[2]);
+                    cv[3] = fma(a0, b3, cv[3]);
+                    cv[0] = fma(a1, w1, cv[0]);
+                    cv[1] = fma(a1, w2, cv[1]);
+                    cv[2] = fma(a1, b3, cv[2]);
+                    cv[3] = fma(a1, b4, cv[3]);
+                    cv[0] = fma(a2, w2, cv[0]);
+                    cv[1] = fma(a2, b3, cv[1]);
+                    cv[2] = fma(a2, b4, cv[2]);
+                    cv[3] = fma(a2, b5, cv[3]);
+                    cv[0] = fma(a3, b3, cv[0]);
+                    cv[1] = fma(a3, b4, cv[1]);
+                    cv[2] = fma(a3, b5, cv[2]);
+                    cv[3] = fma(a3, b6, cv[3]);
+                    w0 = b4;
+                    w1 = b5;
+                    w2 = b6;
                 }
                 for (; k < k1; ++k) {
-                    const double av = xa[k] - ma, bv = bat(t0 + k + 3);
+                    const double av = sa[k], bv = bw[k + 3];
                     cv[0] = fma(av, w0, cv[0]);
                     cv[1] = fma(av, w1, cv[1]);
                     cv[2] = fma(av, w2, cv[2]);
@@ -570,42 +700,49 @@ __global__ __launch_bounds__(kWave* kFinRows) void k_finalize_topk(MfmaFinJob on
                     w2 = bv;
                 }
             }
-            // the four quarters' sums (lanes Q and 2Q apart within the pick)
+            // the four quarters' sums: lanes Q and 2Q apart within the pick
+            // (16 lanes per pick: rotations of the DPP row by 4 and 8)
+            if (L == 16) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                cv[r] += __shfl_xor(cv[r], Q, kWave);
-                cv[r] += __shfl_xor(cv[r], 2 * Q, kWave);
+                for (int r = 0; r < 4; ++r) {
+                    cv[r] += dpp_f64<kDppRor4>(cv[r]);
+                    cv[r] += dpp_f64<kDppRor8>(cv[r]);
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    cv[r] += __shfl_xor(cv[r], Q, kWave);
+                    cv[r] += __shfl_xor(cv[r], 2 * Q, kWave);
+                }
             }
             double dd = INFINITY;
             int64_t tt = INT64_MAX;
-            if (base >= 0 && kq == 0) {
-                const double sa = gptr(J.asig)[i];
+            if (fin && wfl == 0) {
+                const double cw = kq == 0 ? cv[0] : kq == 1 ? cv[1] : kq == 2 ? cv[2] : cv[3];
+                const double rho = cw / ((double)m * sa_ * wsig);
+                dd = sqrt(fmax(0.0, 2.0 * (double)m * (1.0 - rho)));
+                tt = tw;
+            }
+            // wave argmin of (distance, window); lanes without a window hold
+            // +inf: each row of 16 lanes on the DPP path, then the four rows
+            argmin_step<kDppXor1>(dd, tt);
+            argmin_step<kDppXor2>(dd, tt);
+            argmin_step<kDppHalfMirror>(dd, tt);
+            argmin_step<kDppRor8>(dd, tt);
+            double bd = __longlong_as_double((long long)lane_u64((unsigned long long)__double_as_longlong(dd), 0));
+            int64_t bt = (int64_t)lane_u64((unsigned long long)tt, 0);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int64_t t = t0 + r;
-                    if (t >= 0 && t < J.WB && bflags[t] == 0) {
-                        const double rho = cv[r] / ((double)m * sa * gptr(J.bsig)[t]);
-                        const double dt = sqrt(fmax(0.0, 2.0 * (double)m * (1.0 - rho)));
-                        if (dt < dd) {  // windows in increasing order: ties keep the smaller
-                            dd = dt;
-                            tt = t;
-                        }
-                    }
+            for (int rr = 16; rr < kWave; rr += 16) {
+                const double od = __longlong_as_double((long long)lane_u64((unsigned long long)__double_as_longlong(dd), rr));
+                const int64_t ot = (int64_t)lane_u64((unsigned long long)tt, rr);
+                if (od < bd || (od == bd && ot < bt)) {
+                    bd = od;
+                    bt = ot;
                 }
             }
-            // wave argmin of (distance, window); lanes without a window hold +inf
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) {
-                const double od = __shfl_xor(dd, off, kWave);
-                const int64_t ot = __shfl_xor(tt, off, kWave);
-                if (od < dd || (od == dd && ot < tt)) {
-                    dd = od;
-                    tt = ot;
-                }
-            }
-            if (tt != INT64_MAX) {
-                d = dd;
-                j = tt;
+            if (bt != INT64_MAX) {
+                d = bd;
+                j = bt;
             }
         }
         if (ff != kNone) {
@@ -847,8 +984,12 @@ int join_mfma_run(const SeriesDev& A, const SeriesDev& B, const MfmaPlan& p, int
         ABJ_TRY(fill_u64(cand, p.nqblk * 32 * p.nchunks * p.K, 0ull, stream));
     }
     const MfmaFinJob fj = fin_job(A, B, p, cand, refine, pearson, P, I, 0);
-    hipLaunchKernelGGL(k_finalize_topk, dim3((unsigned)fin_blocks(fj)), dim3(kWave * kFinRows), 0, stream, fj,
-                       nullptr, 1);
+    if (p.keep <= 4)
+        hipLaunchKernelGGL(k_finalize_topk<4>, dim3((unsigned)fin_blocks(fj)), dim3(kWave * kFinRows), 0, stream,
+                           fj, nullptr, 1);
+    else
+        hipLaunchKernelGGL(k_finalize_topk<8>, dim3((unsigned)fin_blocks(fj)), dim3(kWave * kFinRows), 0, stream,
+                           fj, nullptr, 1);
     ABJ_HIP(hipGetLastError());
     return ABJ_OK;
 }
@@ -882,6 +1023,7 @@ void mfma_batch_prepare(const MfmaBatchItem* items, int n, int tier, int refine,
         ob += op_blocks(oj[a]);
         fj[a] = fin_job(it.A, *it.B, it.plan, it.cand, refine, pearson, it.P, it.I, fb);
         fb += fin_blocks(fj[a]);
+        if (fj[a].keep > L->max_keep) L->max_keep = fj[a].keep;
         if (!sweep && it.A.W > 0) L->empty.push_back(a);
         if (!sweep) continue;
         size_t g = 0;
@@ -917,8 +1059,13 @@ int mfma_batch_launch(const MfmaBatchItem* items, const void* dev, const MfmaBat
     for (const auto& gr : L.groups)
         ABJ_TRY(launch_join(L.tier, gr.ks, gr.k, MfmaJoinJob{}, jj + gr.first, gr.count, gr.blocks, stream));
     if (L.fin_blocks > 0) {
-        hipLaunchKernelGGL(k_finalize_topk, dim3((unsigned)L.fin_blocks), dim3(kWave * kFinRows), 0, stream,
-                           MfmaFinJob{}, reinterpret_cast<const MfmaFinJob*>(d + L.off_fin), L.n);
+        const auto* fj = reinterpret_cast<const MfmaFinJob*>(d + L.off_fin);
+        if (L.max_keep <= 4)
+            hipLaunchKernelGGL(k_finalize_topk<4>, dim3((unsigned)L.fin_blocks), dim3(kWave * kFinRows), 0, stream,
+                               MfmaFinJob{}, fj, L.n);
+        else
+            hipLaunchKernelGGL(k_finalize_topk<8>, dim3((unsigned)L.fin_blocks), dim3(kWave * kFinRows), 0, stream,
+                               MfmaFinJob{}, fj, L.n);
         ABJ_HIP(hipGetLastError());
     }
     return ABJ_OK;

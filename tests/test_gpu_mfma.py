@@ -114,6 +114,23 @@ def test_flat_nonfinite_degenerate(orc, tier):
     assert np.all(np.isnan(P) | np.isinf(P)) and np.all(I == -1)
 
 
+@pytest.mark.parametrize("tier", TIERS)
+def test_rows_with_fewer_candidates_than_picks(orc, tier):
+    # references of a few windows: every candidate of a row lies within the
+    # re-check radius of the best, so fewer picks are taken than allowed and
+    # the lanes of the missing picks must stay idle.  A larger join runs first
+    # so that the re-check's LDS holds samples of another launch.
+    w = synth.WORKLOADS["rw2k_m100"]()
+    run(w["query"], w["dict"], w["bounds"], w["m"], tier)
+    rng = np.random.default_rng(77)
+    m = 64
+    q = synth.random_walk(3000, rng)
+    d = synth.random_walk(m + 5, rng)  # 6 windows
+    check(orc, q, d, [0, len(d)], m, tier)
+    d2 = synth.random_walk(2 * (m + 2), rng)  # two segments of 3 windows
+    check(orc, q, d2, [0, m + 2, 2 * (m + 2)], m, tier)
+
+
 def test_refine_k_values(orc):
     w = synth.WORKLOADS["rw2k_m100"]()
     for k in (1, 2, 3, 8):

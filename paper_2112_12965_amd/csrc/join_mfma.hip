@@ -285,24 +285,25 @@ __global__ __launch_bounds__(kWave* NW) __attribute__((amdgpu_waves_per_eu(WPE))
     }
 
     // stage s holds dictionary blocks db_lo + s G .. + G - 1, fragment order
-    // (block, ks, lane) exactly as in global memory, so the copy is linear;
-    // every lane issues all its loads, so the loads in flight are known at
-    // compile time (past the chunk the address is clamped: those blocks have
-    // mask 0 and are never used)
-    V8 pre[kPerThread];
-    auto fetch = [&](int64_t s) {
+    // (block, ks, lane) exactly as in global memory, so the copy is linear.
+    // The fragments go from global memory straight into LDS (each wave's 64
+    // lanes fill 1 KB): no registers hold them in flight, and they are waited
+    // for (vmcnt) before the barrier that ends the stage.  Every lane issues
+    // all its loads; past the chunk the address is clamped (those blocks have
+    // mask 0 and are never used).
+    auto fetch = [&](int64_t s, int into) {
         const int64_t base = (db_lo + s * G) * KS * kWave;
         const int64_t lim = db_hi * KS * kWave;
 #pragma unroll
         for (int e = 0; e < kPerThread; ++e) {
             const int64_t f = base + (int64_t)e * (kWave * NW) + threadIdx.x;
-            pre[e] = zd[f < lim ? f : lim - 1];
+            __builtin_amdgcn_global_load_lds(
+                (const void*)(zd + (f < lim ? f : lim - 1)),
+                (__attribute__((address_space(3))) void*)&stage[into][e * (kWave * NW) + wave * kWave], 16, 0, 0);
         }
     };
-    auto store = [&](int buf) {
-#pragma unroll
-        for (int e = 0; e < kPerThread; ++e) stage[buf][e * (kWave * NW) + threadIdx.x] = pre[e];
-    };
+    // vmcnt(0), the other counters left alone
+    auto wait_loads = [] { __builtin_amdgcn_s_waitcnt(0x0F70); };
     // the masks of a stage's G blocks, one per lane (0 past the chunk),
     // loaded one stage ahead with the fragments and read with readlane (a
     // scalar load per block shares its wait counter with the LDS reads)
@@ -314,15 +315,15 @@ __global__ __launch_bounds__(kWave* NW) __attribute__((amdgpu_waves_per_eu(WPE))
 
     __builtin_assume(nst > 0);  // every chunk holds a block (mfma_plan)
     fetch_mask(0);
-    fetch(0);
-    store(0);
+    fetch(0, 0);
+    wait_loads();
     __syncthreads();
     for (int64_t s = 0; s < nst; ++s) {
         const int buf = (int)(s & 1);
         smask = smask_next;
         if (s + 1 < nst) {
             fetch_mask(s + 1);
-            fetch(s + 1);
+            fetch(s + 1, buf ^ 1);  // its readers passed the barrier that ended stage s - 1
         }
         for (int g0 = 0; g0 < G; g0 += 2) {
             uint32_t msk[2];
@@ -330,16 +331,33 @@ __global__ __launch_bounds__(kWave* NW) __attribute__((amdgpu_waves_per_eu(WPE))
             for (int h = 0; h < 2; ++h) msk[h] = __builtin_amdgcn_readlane(smask, g0 + h);
             if ((msk[0] | msk[1]) == 0u) continue;  // both blocks masked or past the end
             f32x16 acc[2][NB];
+            if constexpr (KS <= 4) {
+                // every fragment of the step read before the first product, so
+                // the LDS latency is paid once per step
+                V8 ad[2][KS];
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks) {
-                V8 ad[2];
+                for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-                for (int h = 0; h < 2; ++h) ad[h] = stage[buf][((g0 + h) * KS + ks) * kWave + lane];
+                    for (int h = 0; h < 2; ++h) ad[h][ks] = stage[buf][((g0 + h) * KS + ks) * kWave + lane];
 #pragma unroll
-                for (int h = 0; h < 2; ++h)
+                for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-                    for (int nb = 0; nb < NB; ++nb)
-                        acc[h][nb] = mfma(ad[h], bq[nb][ks], ks == 0 ? f32x16{} : acc[h][nb]);
+                    for (int h = 0; h < 2; ++h)
+#pragma unroll
+                        for (int nb = 0; nb < NB; ++nb)
+                            acc[h][nb] = mfma(ad[h][ks], bq[nb][ks], ks == 0 ? f32x16{} : acc[h][nb]);
+            } else {
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) {
+                    V8 ad[2];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) ad[h] = stage[buf][((g0 + h) * KS + ks) * kWave + lane];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+#pragma unroll
+                        for (int nb = 0; nb < NB; ++nb)
+                            acc[h][nb] = mfma(ad[h], bq[nb][ks], ks == 0 ? f32x16{} : acc[h][nb]);
+                }
             }
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
@@ -397,7 +415,7 @@ __global__ __launch_bounds__(kWave* NW) __attribute__((amdgpu_waves_per_eu(WPE))
                 }
             }
         }
-        if (s + 1 < nst) store(buf ^ 1);
+        wait_loads();
         __syncthreads();
     }
     // merge the two lane halves (same query window, disjoint dictionary rows)

@@ -320,42 +320,51 @@ def serving(abjoin, synth, tiers, n_req: int, fracs=(0.5, 0.8, 0.95)):
     """Serving workload: a resident dictionary of 64 x 1,000 ECG-like samples;
     requests with log-uniform lengths in [1,024, 65,536] and m drawn from
     {64, 128, 256}.  Saturation throughput first (all requests at once), then
-    Poisson arrivals at fractions of the saturation rate; p50/p99 latency from
-    submit to results on the host."""
+    Poisson arrivals at fractions of the saturation rate on the same server
+    (warm: its staging buffers have grown to the largest batch); p50/p99
+    latency from submit to results on the host.  A fresh server's first run
+    at the lowest load is reported beside them (cold start: the first batches
+    allocate the staging buffers)."""
     import threading
+
+    import numpy as np
 
     w = synth.WORKLOADS["serve_dict64x1000"]()
     dct = abjoin.Dictionary(w["dict"], w["bounds"], (64, 128, 256))
     pool = synth.ecg_like(1 << 22, synth.rng_for(3, 0))
     out = {"workload": "serve_dict64x1000", "requests": n_req, "dict_segments": 64, "segment_samples": 1000,
            "query_samples": "log-uniform 1024..65536", "m": [64, 128, 256], "tiers": {}}
+
+    def run(srv, qps):
+        """One pass of n_req requests; figures from the requests' own timestamps."""
+        sched = synth.serving_schedule(n_req, qps if qps else 1e9, synth.rng_for(4, int(qps or 0)))
+        offs = synth.rng_for(4, 99).integers(0, len(pool) - 65536, n_req)
+        ids = [None] * n_req
+        t0 = time.perf_counter()
+
+        def feeder():
+            for k, r in enumerate(sched):
+                if qps:
+                    dt = r.arrival_s - (time.perf_counter() - t0)
+                    if dt > 0:
+                        time.sleep(dt)
+                ids[k] = srv.submit(pool[offs[k]:offs[k] + r.length], r.m)
+
+        th = threading.Thread(target=feeder)
+        th.start()
+        th.join()
+        assert srv.drain(600000) == abjoin.ABJ_OK
+        st = [srv.result(i)[2] for i in ids]
+        assert all(x["status"] == abjoin.ABJ_OK for x in st)
+        lat = np.array([x["t_done"] - x["t_arrive"] for x in st])
+        busy = max(x["t_done"] for x in st) - min(x["t_start"] for x in st)
+        return {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+                "max_s": float(lat.max()), "pairs": int(sum(x["pairs"] for x in st)), "busy_s": busy,
+                "completed": len(st), "batches": len({x["batch"] for x in st})}
+
     for tier in tiers:
-        def run(qps):
-            sched = synth.serving_schedule(n_req, qps if qps else 1e9, synth.rng_for(4, int(qps or 0)))
-            offs = synth.rng_for(4, 99).integers(0, len(pool) - 65536, n_req)
-            srv = abjoin.Server(dct, tier=tier, max_slots=512, mem_budget=2 << 30)
-            ids = [None] * n_req
-            t0 = time.perf_counter()
-
-            def feeder():
-                for k, r in enumerate(sched):
-                    if qps:
-                        dt = r.arrival_s - (time.perf_counter() - t0)
-                        if dt > 0:
-                            time.sleep(dt)
-                    ids[k] = srv.submit(pool[offs[k]:offs[k] + r.length], r.m)
-
-            th = threading.Thread(target=feeder)
-            th.start()
-            th.join()
-            assert srv.drain(600000) == abjoin.ABJ_OK
-            st = srv.stats()
-            for i in ids:
-                srv.result(i)
-            srv.close()
-            return st
-
-        sat = run(None)
+        srv = abjoin.Server(dct, tier=tier, max_slots=512, mem_budget=2 << 30)
+        sat = run(srv, None)
         sat_qps = sat["completed"] / sat["busy_s"]
         # the same request set joined one at a time through the resident
         # dictionary (one stream, one request per call), for comparison
@@ -375,14 +384,20 @@ def serving(abjoin, synth, tiers, n_req: int, fracs=(0.5, 0.8, 0.95)):
                "batches": sat["batches"], "one_shot_pairs_per_s": sat["pairs"] / one_s,
                "served_vs_one_shot": (sat["pairs"] / sat["busy_s"]) / (sat["pairs"] / one_s), "levels": []}
         for f in fracs:
-            st = run(f * sat_qps)
+            st = run(srv, f * sat_qps)
             rec["levels"].append({"qps": f * sat_qps, "load": f, "p50_ms": st["p50_s"] * 1e3,
                                   "p99_ms": st["p99_s"] * 1e3, "max_ms": st["max_s"] * 1e3,
                                   "pairs_per_s": st["pairs"] / st["busy_s"], "batches": st["batches"]})
+        srv.close()
+        cold_srv = abjoin.Server(dct, tier=tier, max_slots=512, mem_budget=2 << 30)
+        cold = run(cold_srv, fracs[0] * sat_qps)
+        cold_srv.close()
+        rec["cold_start"] = {"load": fracs[0], "p50_ms": cold["p50_s"] * 1e3, "p99_ms": cold["p99_s"] * 1e3,
+                             "max_ms": cold["max_s"] * 1e3}
         out["tiers"][tier] = rec
         log(f"serving {tier}: saturation {rec['saturation_pairs_per_s']:.3e} pairs/s "
             f"({rec['served_vs_one_shot']:.2f}x one request at a time), "
-            f"p99 at 50% load {rec['levels'][0]['p99_ms']:.2f} ms")
+            f"p99 at 50% load {rec['levels'][0]['p99_ms']:.2f} ms (cold server {rec['cold_start']['p99_ms']:.2f} ms)")
     dct.close()
     return out
 

@@ -131,6 +131,24 @@ def test_rows_with_fewer_candidates_than_picks(orc, tier):
     check(orc, q, d2, [0, m + 2, 2 * (m + 2)], m, tier)
 
 
+@pytest.mark.parametrize("tier", TIERS)
+@pytest.mark.parametrize("m", [100, 256])
+def test_eight_picks_meet_the_bar(orc, tier, m):
+    # refine_k = 8: eight candidates per lane half and eight picks of 8
+    # windows each (a stage of 2,104 reference samples per row); at least as
+    # many windows re-checked near the best scores as with four picks, so the
+    # same bar holds
+    rng = np.random.default_rng(4100 + m)
+    q = synth.ecg_like(4000, rng, n_anomalies=2)
+    d = synth.ecg_like(3001, rng)
+    bounds = [0, 1400, 1400 + m - 1, 3001]
+    print(f"[case] refine_k=8 n_q={len(q)} n_d={len(d)} m={m} tier={tier}", flush=True)
+    P, I = run(q, d, bounds, m, tier, refine_k=8)
+    Po, Io, P2o = orc.ab_join(q, d, bounds, m, second=True)
+    st = _parity.compare(P, I, Po, Io, P2o, TOL, orc, q, d, m, bounds)
+    print(tier, m, st, flush=True)
+
+
 def test_refine_k_values(orc):
     w = synth.WORKLOADS["rw2k_m100"]()
     for k in (1, 2, 3, 8):

@@ -205,15 +205,20 @@ __device__ inline float stamp(float x, int v)
     return __uint_as_float((__float_as_uint(x) & ~15u) | (unsigned)(15 - v));
 }
 
-// Largest of 16 values (NaN-free inputs; the compiler forms max3 chains).
+// Largest of 16 values.  The inputs are never NaN (finite matrix-core
+// results, their stamped forms, kNoScore), so IEEE maximum (which would
+// propagate a NaN) equals the usual fmaxf here; it maps onto gfx950's
+// three-input v_maximum3_f32 without the operand canonicalisations fmaxf
+// needs: 8 instructions for the 16 values.
+__device__ inline float max2(float a, float b) { return __builtin_elementwise_maximum(a, b); }
 __device__ inline float max16(const float (&a)[16])
 {
-    const float m0 = fmaxf(fmaxf(a[0], a[1]), a[2]);
-    const float m1 = fmaxf(fmaxf(a[3], a[4]), a[5]);
-    const float m2 = fmaxf(fmaxf(a[6], a[7]), a[8]);
-    const float m3 = fmaxf(fmaxf(a[9], a[10]), a[11]);
-    const float m4 = fmaxf(fmaxf(a[12], a[13]), a[14]);
-    return fmaxf(fmaxf(fmaxf(fmaxf(m0, m1), m2), fmaxf(m3, m4)), a[15]);
+    const float m0 = max2(max2(a[0], a[1]), a[2]);
+    const float m1 = max2(max2(a[3], a[4]), a[5]);
+    const float m2 = max2(max2(a[6], a[7]), a[8]);
+    const float m3 = max2(max2(a[9], a[10]), a[11]);
+    const float m4 = max2(max2(a[12], a[13]), a[14]);
+    return max2(max2(max2(m0, m1), m2), max2(max2(m3, m4), a[15]));
 }
 
 // Row index (within the 32-window block) of accumulator v in lane `lane`.

@@ -245,7 +245,9 @@ __global__ __launch_bounds__(kWave* NW) __attribute__((amdgpu_waves_per_eu(WPE))
     MfmaJoinJob one, const MfmaJoinJob* __restrict__ jobs, int njobs)
 {
     using V8 = typename Vec8<T>::type;
-    constexpr int G = 32 / KS;                   // dictionary blocks per stage
+    // dictionary blocks per stage: 32 KB of fragments, 64 KB at KS = 16 (one
+    // workgroup per CU there, so the two buffers fit in LDS: 2 steps per barrier)
+    constexpr int G = (KS == 16 ? 64 : 32) / KS;
     constexpr int kFrag = G * KS * kWave;        // 16-byte fragments per stage
     constexpr int kPerThread = kFrag / (kWave * NW);
     static_assert(G % 2 == 0, "two blocks per step");

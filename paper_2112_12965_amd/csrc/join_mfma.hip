@@ -245,9 +245,9 @@ __global__ __launch_bounds__(kWave* NW) __attribute__((amdgpu_waves_per_eu(WPE))
     MfmaJoinJob one, const MfmaJoinJob* __restrict__ jobs, int njobs)
 {
     using V8 = typename Vec8<T>::type;
-    // dictionary blocks per stage: 32 KB of fragments, 64 KB at KS = 16 (one
-    // workgroup per CU there, so the two buffers fit in LDS: 2 steps per barrier)
-    constexpr int G = (KS == 16 ? 64 : 32) / KS;
+    // dictionary blocks per stage: 32 KB of fragments, 64 KB at KS >= 8 (one
+    // workgroup per CU there, so the two buffers fit in LDS: fewer barriers)
+    constexpr int G = (KS >= 8 ? 64 : 32) / KS;
     constexpr int kFrag = G * KS * kWave;        // 16-byte fragments per stage
     constexpr int kPerThread = kFrag / (kWave * NW);
     static_assert(G % 2 == 0, "two blocks per step");
@@ -817,7 +817,7 @@ int launch_ks(int KS, int K, const MfmaJoinJob& one, const MfmaJoinJob* jobs, in
         case 1: return launch_k<T, 1, 1, 8, 4>(K, one, jobs, njobs, blocks, stream);
         case 2: return launch_k<T, 2, 1, 8, 4>(K, one, jobs, njobs, blocks, stream);
         case 4: return launch_k<T, 4, 1, 8, 4>(K, one, jobs, njobs, blocks, stream);
-        case 8: return launch_k<T, 8, 2, 4, 2>(K, one, jobs, njobs, blocks, stream);
+        case 8: return launch_k<T, 8, 2, 8, 2>(K, one, jobs, njobs, blocks, stream);
         case 16: return launch_k<T, 16, 1, 8, 2>(K, one, jobs, njobs, blocks, stream);
         default: return set_error(ABJ_EINVAL, "unsupported k-step count %d", KS);
     }
@@ -914,7 +914,7 @@ int64_t fin_blocks(const MfmaFinJob& j) { return (j.WA + kFinRows - 1) / kFinRow
 static void mfma_shape(int KS, int* nb, int* nw)
 {
     *nb = KS == 8 ? 2 : 1;
-    *nw = KS == 8 ? 4 : 8;
+    *nw = 8;
 }
 
 int mfma_plan(int64_t WA, int64_t WB, int32_t m, int tier, int refine_k, MfmaPlan* p)

@@ -245,9 +245,10 @@ __global__ __launch_bounds__(kWave* NW) __attribute__((amdgpu_waves_per_eu(WPE))
     MfmaJoinJob one, const MfmaJoinJob* __restrict__ jobs, int njobs)
 {
     using V8 = typename Vec8<T>::type;
-    // dictionary blocks per stage: 32 KB of fragments, 64 KB at KS >= 8 (one
-    // workgroup per CU there, so the two buffers fit in LDS: fewer barriers)
-    constexpr int G = (KS >= 8 ? 64 : 32) / KS;
+    // dictionary blocks per stage: 32 KB of fragments, 64 KB with 2 waves per
+    // SIMD (one workgroup per CU then, so the two buffers fit in LDS: fewer
+    // barriers)
+    constexpr int G = (WPE <= 2 ? 64 : 32) / KS;
     constexpr int kFrag = G * KS * kWave;        // 16-byte fragments per stage
     constexpr int kPerThread = kFrag / (kWave * NW);
     static_assert(G % 2 == 0, "two blocks per step");
@@ -816,7 +817,7 @@ int launch_ks(int KS, int K, const MfmaJoinJob& one, const MfmaJoinJob* jobs, in
     switch (KS) {
         case 1: return launch_k<T, 1, 1, 8, 4>(K, one, jobs, njobs, blocks, stream);
         case 2: return launch_k<T, 2, 1, 8, 4>(K, one, jobs, njobs, blocks, stream);
-        case 4: return launch_k<T, 4, 1, 8, 4>(K, one, jobs, njobs, blocks, stream);
+        case 4: return launch_k<T, 4, 2, 8, 2>(K, one, jobs, njobs, blocks, stream);
         case 8: return launch_k<T, 8, 2, 8, 2>(K, one, jobs, njobs, blocks, stream);
         case 16: return launch_k<T, 16, 1, 8, 2>(K, one, jobs, njobs, blocks, stream);
         default: return set_error(ABJ_EINVAL, "unsupported k-step count %d", KS);
@@ -913,7 +914,7 @@ int64_t fin_blocks(const MfmaFinJob& j) { return (j.WA + kFinRows - 1) / kFinRow
 // NB and NW of each k-step count (see launch_ks).
 static void mfma_shape(int KS, int* nb, int* nw)
 {
-    *nb = KS == 8 ? 2 : 1;
+    *nb = KS == 4 || KS == 8 ? 2 : 1;
     *nw = 8;
 }
 

@@ -944,13 +944,14 @@ int mfma_plan(int64_t WA, int64_t WB, int32_t m, int tier, int refine_k, MfmaPla
     p->ndblk = (WB + 31) / 32;
     const int64_t qblk_per_panel = (int64_t)NW * NB;
     p->npanels = (p->nqblk + qblk_per_panel - 1) / qblk_per_panel;
-    // split the dictionary sweep until the workgroups fill the chip once (512
-    // workgroups of 4-8 waves: 4 waves per SIMD), but keep at least 64 blocks
-    // (2,048 windows) per chunk: a shorter sweep spends more of its blocks
-    // before its top-K thresholds settle, when nearly every block takes the
-    // insert path
+    // split the dictionary sweep until the workgroups fill the chip once (two
+    // 8-wave workgroups per CU at KS <= 2, one with the 64 KB stages of KS >= 4:
+    // 512 or 256 on 256 CUs), but keep at least 64 blocks (2,048 windows) per
+    // chunk: a shorter sweep spends more of its blocks before its top-K
+    // thresholds settle, when nearly every block takes the insert path
+    const int64_t fill = KS <= 2 ? 512 : 256;
     int64_t nchunks = 1;
-    while (p->npanels * nchunks < 512 && (p->ndblk + nchunks * 2 - 1) / (nchunks * 2) >= 64) nchunks *= 2;
+    while (p->npanels * nchunks < fill && (p->ndblk + nchunks * 2 - 1) / (nchunks * 2) >= 64) nchunks *= 2;
     while (nchunks * K > 512) nchunks /= 2;  // the re-check reads at most 512 candidates per row
     // a reference shorter than m has no block: one empty chunk (no sweep)
     p->blk_per_chunk = p->ndblk > 0 ? (p->ndblk + nchunks - 1) / nchunks : 1;

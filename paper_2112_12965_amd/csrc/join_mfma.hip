@@ -533,10 +533,11 @@ __device__ __forceinline__ void argmin_step(double& d, int64_t& t)
 // reads across rows.  With `refine` off, report the distance implied by the
 // best 16-bit score instead.  Flat / non-finite conventions as in the FP32
 // tier.  kMaxPick: the largest `keep` of the launch's jobs (4 or 8), which
-// sizes the stage (10.5 or 18.4 KiB per wave).
+// sizes the stage (10.5 or 18.4 KiB per wave; the larger stage leaves room for
+// 2 waves per SIMD, and the register budget follows).
 template <int kMaxPick>
-__global__ __launch_bounds__(kWave* kFinRows) __attribute__((amdgpu_waves_per_eu(4))) void k_finalize_topk(
-    MfmaFinJob one, const MfmaFinJob* __restrict__ jobs, int njobs)
+__global__ __launch_bounds__(kWave* kFinRows) __attribute__((amdgpu_waves_per_eu(kMaxPick <= 4 ? 4 : 2)))
+void k_finalize_topk(MfmaFinJob one, const MfmaFinJob* __restrict__ jobs, int njobs)
 {
     // per wave: the row (256 doubles), then kMaxPick spans of up to
     // m + 64 / kMaxPick - 1 reference samples (one pick of 64 lanes: m + 63)

@@ -478,6 +478,10 @@ __device__ __forceinline__ unsigned long long lane_u64(unsigned long long v, int
     const unsigned hi = (unsigned)__builtin_amdgcn_readlane((unsigned)(v >> 32), l);
     return ((unsigned long long)hi << 32) | lo;
 }
+__device__ __forceinline__ double lane_f64(double v, int l)
+{
+    return __longlong_as_double((long long)lane_u64((unsigned long long)__double_as_longlong(v), l));
+}
 // The largest key of the wave (of its first 16 lanes if kRows is 1), wave-
 // uniform: each row of 16 lanes on the DPP path, then the rows' results
 // through scalar reads.
@@ -756,11 +760,11 @@ void k_finalize_topk(MfmaFinJob one, const MfmaFinJob* __restrict__ jobs, int nj
             argmin_step<kDppXor2>(dd, tt);
             argmin_step<kDppHalfMirror>(dd, tt);
             argmin_step<kDppRor8>(dd, tt);
-            double bd = __longlong_as_double((long long)lane_u64((unsigned long long)__double_as_longlong(dd), 0));
+            double bd = lane_f64(dd, 0);
             int64_t bt = (int64_t)lane_u64((unsigned long long)tt, 0);
 #pragma unroll
             for (int rr = 16; rr < kWave; rr += 16) {
-                const double od = __longlong_as_double((long long)lane_u64((unsigned long long)__double_as_longlong(dd), rr));
+                const double od = lane_f64(dd, rr);
                 const int64_t ot = (int64_t)lane_u64((unsigned long long)tt, rr);
                 if (od < bd || (od == bd && ot < bt)) {
                     bd = od;

@@ -428,7 +428,8 @@ extern "C" int dict_build(const double* series, int64_t n, int32_t m, const abj_
     L.m = m;
     const int64_t Lmin = std::max<int64_t>(m, std::min<int64_t>(n, (int64_t)ceil(o.context * (double)m)));
     L.max_dseg = n / (Lmin + 1) + 1;  // merged segments are disjoint and do not touch
-    L.dict_ws_bytes = stats_scratch_bytes(n, W) + fp32_chunk_bytes((int32_t)std::min<int64_t>(L.max_dseg, INT32_MAX), n) + 256;
+    const int32_t most_seg = (int32_t)std::min<int64_t>(L.max_dseg, INT32_MAX);
+    L.dict_ws_bytes = stats_scratch_bytes(n, W) + fp32_chunk_bytes(most_seg, n) + 256;
     Arena ar(stream);
     ar.reserve(series_stats_bytes(n, W));
     ar.reserve(sizeof(unsigned long long) * (size_t)W);  // keys

@@ -62,6 +62,7 @@ struct SeriesDev {
     // each inside the valid windows of one segment (see fp32_chunks_upload)
     const int32_t* chunks = nullptr;
     int64_t nchunks = 0;
+    int32_t chunk_w = 0;  // the widest chunk (windows), which sizes the tile kernel's LDS
 };
 
 // Stream-ordered scratch arena: one hipMallocAsync block carved into aligned
@@ -179,17 +180,31 @@ struct Fp32Slot {
 void fp32_slot(const SeriesDev& A, const SeriesDev& B, unsigned long long* keys, int64_t tile0, Fp32Slot* sl);
 // Column chunks of a reference of n samples with these segments (host
 // bounds; n_seg = 0 means one segment): every valid window of a segment
-// falls in one of its chunks, chunks hold at most 1024 windows, and windows
-// that cross a segment break belong to none, so the engine never sweeps them.
-// Carves the list from `ar` and copies it to the device for B; with dbounds
-// the same copy also brings the segment bounds (*dbounds points at them).
-size_t fp32_chunk_bytes(int32_t n_seg, int64_t n);
+// falls in one of its chunks, chunks hold at most 2048 windows (max_w, when
+// positive and smaller), and windows that cross a segment break belong to
+// none, so the engine never sweeps them.  Carves the list from `ar` and
+// copies it to the device for B; with dbounds the same copy also brings the
+// segment bounds (*dbounds points at them).
+size_t fp32_chunk_bytes(int32_t n_seg, int64_t n, int32_t max_w = 0);
 // The chunk list itself (pairs [start, end) of reference windows), host side.
-std::vector<int32_t> fp32_chunk_list(const int64_t* bounds, int32_t n_seg, int64_t n, int32_t m);
+std::vector<int32_t> fp32_chunk_list(const int64_t* bounds, int32_t n_seg, int64_t n, int32_t m, int32_t max_w = 0);
 int fp32_chunks_upload(const int64_t* bounds, int32_t n_seg, int64_t n, int32_t m, Arena& ar, SeriesDev* B,
-                       hipStream_t stream, int64_t** dbounds = nullptr);
+                       hipStream_t stream, int64_t** dbounds = nullptr, int32_t max_w = 0);
+// One wave sweeps a tile of 1024 query rows by one chunk; a tile's FP64 edges
+// cost its rows plus its columns, so wider chunks cost fewer edge products per
+// pair, but give fewer tiles.  A join takes the 2048-window chunks when they
+// still give at least one tile per workgroup of the persistent grid
+// (kFp32Grid), else chunks of at most kFp32NarrowChunk windows.  The choice
+// depends on the join's own sizes only, so a request joins the same way on its
+// own, through a resident dictionary and served in a batch.
+constexpr int64_t kFp32Grid = 4096;
+constexpr int32_t kFp32NarrowChunk = 1024;
+inline bool fp32_wide_chunks(int64_t WA, int64_t wide_nchunks)
+{
+    return ((WA + kFp32BandRows - 1) / kFp32BandRows) * wide_nchunks >= kFp32Grid;
+}
 int64_t fp32_slot_tiles(const Fp32Slot& sl);
-size_t fp32_lds_bytes(int max_m);
+size_t fp32_lds_bytes(int max_m, int max_w);
 // FP32 diagonal join of every tile of every slot (persistent workgroups, one
 // atomic tile counter); writes one packed (score, group) key per query row.
 // self: the slots are self-joins whose excl fields are honoured.
@@ -197,9 +212,18 @@ size_t fp32_lds_bytes(int max_m);
 // Bytes of the tile counters of one FP32 launch (zero before the launch).
 constexpr int kTileQueues = 16;
 constexpr size_t kTileCounterBytes = kTileQueues * 128;
-int join_fp32_batch(const Fp32Slot* slots_dev, int nslots, int64_t ntiles, int max_m, int64_t pairs,
+// max_m / max_w: the largest window length and chunk width (chunk_w) of the
+// slots, which size the LDS of the launch.
+int join_fp32_batch(const Fp32Slot* slots_dev, int nslots, int64_t ntiles, int max_m, int max_w, int64_t pairs,
                     unsigned long long* counter_dev, hipStream_t stream, bool self = false,
                     bool counter_zeroed = false);
+// The widest chunk of a chunk list (pairs [start, end)).
+inline int32_t fp32_chunk_width(const std::vector<int32_t>& c)
+{
+    int32_t w = 0;
+    for (size_t k = 0; k + 1 < c.size(); k += 2) w = std::max(w, c[k + 1] - c[k]);
+    return w;
+}
 
 // Turns packed keys into P (FP64 re-check, flat conventions) and I; P64
 // (optional) receives the same values unrounded.  excl >= 0 makes it a

@@ -165,13 +165,24 @@ size_t query_scratch_bytes(int64_t n, int32_t m, int64_t WB, const abj_opts& o, 
     return b;
 }
 
+// The FP32 column chunks of a join of WA query windows against this
+// reference: the wide list, or the narrow one when the wide one gives fewer
+// tiles than the grid (fp32_wide_chunks).
+std::vector<int32_t> fp32_join_chunks(const int64_t* bounds, int32_t n_seg, int64_t n, int32_t m, int64_t WA)
+{
+    std::vector<int32_t> c = fp32_chunk_list(bounds, n_seg, n, m);
+    if (!fp32_wide_chunks(WA, (int64_t)c.size() / 2)) c = fp32_chunk_list(bounds, n_seg, n, m, kFp32NarrowChunk);
+    return c;
+}
+
 size_t pair_scratch_bytes(int64_t n_query, int64_t n_ref, int32_t n_seg, int32_t m, const abj_opts& o,
                           const MfmaPlan& plan, size_t part_bytes)
 {
     const int64_t WB = n_ref >= m ? n_ref - m + 1 : 0;
-    return stats_scratch_bytes(n_ref, WB) + fp32_chunk_bytes(n_seg, n_ref) + al256(stats_job_bytes()) +
-           query_scratch_bytes(n_query, m, WB, o, plan) + (o.tier != ABJ_TIER_FP32 ? mfma_dict_bytes(plan) : 0) +
-           part_bytes;
+    // room for either chunk list (the narrow one is the longer)
+    return stats_scratch_bytes(n_ref, WB) + fp32_chunk_bytes(n_seg, n_ref, kFp32NarrowChunk) +
+           al256(stats_job_bytes()) + query_scratch_bytes(n_query, m, WB, o, plan) +
+           (o.tier != ABJ_TIER_FP32 ? mfma_dict_bytes(plan) : 0) + part_bytes;
 }
 
 // The whole path of one join: the statistics of the query (and of the
@@ -190,7 +201,7 @@ int join_run(const double* query, int64_t n, int32_t m, const double* ref, int64
     const int njobs = ref ? 2 : 1;
     const size_t jb = stats_job_bytes();
     std::vector<int32_t> chunks;
-    if (ref) chunks = fp32_chunk_list(ref_bounds, n_seg, n_ref, m);
+    if (ref) chunks = fp32_join_chunks(ref_bounds, n_seg, n_ref, m, n - m + 1);
     const size_t nb = ref ? (size_t)(n_seg + 1) : 0;
     const size_t o_chunks = sizeof(int64_t) * nb;
     const size_t o_jobs = al256(o_chunks + sizeof(int32_t) * chunks.size());
@@ -208,6 +219,7 @@ int join_run(const double* query, int64_t n, int32_t m, const double* ref, int64
                         reinterpret_cast<const int64_t*>(U), n_seg);
         B.chunks = reinterpret_cast<const int32_t*>(U + o_chunks);
         B.nchunks = (int64_t)chunks.size() / 2;
+        B.chunk_w = fp32_chunk_width(chunks);
         for (int32_t sgi = 0; sgi < n_seg; ++sgi) {
             const int64_t len = ref_bounds[sgi + 1] - ref_bounds[sgi];
             if (len >= m) B.nvalid += len - m + 1;
@@ -234,8 +246,8 @@ int join_run(const double* query, int64_t n, int32_t m, const double* ref, int64
     ABJ_TRY(stats_launch_many(U + o_jobs, njobs, bs, bl, bw, stream));
     if (!fp32)
         return join_mfma_run(A, B, plan, !(o.flags & ABJ_FLAG_NO_REFINE), pearson, P, I, ar, stream, dop);
-    ABJ_TRY(join_fp32_batch(reinterpret_cast<const Fp32Slot*>(U + o_slot), 1, fp32_slot_tiles(sl), m, sl.pairs,
-                            reinterpret_cast<unsigned long long*>(U + o_counter), stream, false, true));
+    ABJ_TRY(join_fp32_batch(reinterpret_cast<const Fp32Slot*>(U + o_slot), 1, fp32_slot_tiles(sl), m, B.chunk_w,
+                            sl.pairs, reinterpret_cast<unsigned long long*>(U + o_counter), stream, false, true));
     if (part && sl.nchunks > kEpiloguePartsMax) {
         ABJ_TRY(fp32_reduce_parts(part, sl.nchunks, A.W, keys, stream));
         part = nullptr;
@@ -350,7 +362,7 @@ int ab_join_validate(const double* query, int64_t n_query, const double* dict, i
     // per-chunk keys instead of atomics when the chunk list is short
     size_t part_bytes = 0;
     if (o.tier == ABJ_TIER_FP32 && WB > 0)
-        part_bytes = fp32_partial_bytes(WA, (int64_t)fp32_chunk_list(seg_bounds, n_seg, n_dict, m).size() / 2);
+        part_bytes = fp32_partial_bytes(WA, (int64_t)fp32_join_chunks(seg_bounds, n_seg, n_dict, m, WA).size() / 2);
     jp->o = o;
     jp->plan = plan;
     jp->part_bytes = part_bytes;

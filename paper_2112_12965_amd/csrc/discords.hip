@@ -278,7 +278,7 @@ extern "C" int discords(const double* query, int64_t n_query, int32_t m, const f
             ABJ_TRY(fill_u64(keys, W, 0ull, stream));
             ABJ_HIP(hipMemcpyAsync(dslots, slots.data(), sizeof(Fp32Slot) * slots.size(), hipMemcpyHostToDevice,
                                    stream));
-            ABJ_TRY(join_fp32_batch(dslots, (int)slots.size(), tiles, m, pairs, counter, stream));
+            ABJ_TRY(join_fp32_batch(dslots, (int)slots.size(), tiles, m, B.chunk_w, pairs, counter, stream));
             for (size_t k = 0; k < runs.size(); ++k) {
                 const int64_t r0 = runs[k].first * kFp32BandRows;
                 ABJ_TRY(finalize_launch(views[k], B, keys + r0, Pmix + r0, Iex + r0, stream));

@@ -10,7 +10,7 @@
 //   cov(i+1, j+1) = cov(i, j) + df_a(i) dg_b(j) + df_b(j) dg_a(i).
 //
 // Work decomposition (one 64-lane wave per tile, no inter-wave traffic):
-//   * a tile is 1024 query rows x one chunk of at most 1024 reference columns;
+//   * a tile is 1024 query rows x one chunk of at most 2048 reference columns;
 //     chunks come from a host-made list and lie inside one segment's valid
 //     windows, so windows that cross a segment break are never swept;
 //   * lane l owns rows i0 + 16 l .. i0 + 16 l + 15 and keeps their covariance
@@ -48,9 +48,11 @@ constexpr int kR = 16;                  // query rows per lane
 constexpr int kB = 16;                  // columns per sweep block (= candidate group of the epilogue)
 constexpr int kBandRows = kR * kWave;   // query rows per tile
 static_assert(kBandRows == kFp32BandRows, "band height is part of the engine's interface");
-constexpr int kTC = 1024;               // reference columns per tile
-constexpr int kQ = kTC / kWave;         // top-edge columns per lane
+constexpr int kTC = 2048;               // reference columns per tile
+constexpr int kQ = 16;                  // top-edge columns per lane in one pass
+constexpr int kEdgePass = kQ * kWave;   // top-edge columns per pass
 static_assert(kR == 16 && kQ == 16, "the edge dot products read the 16-row copies: lanes 16 samples apart");
+static_assert(kTC % kEdgePass == 0, "whole top-edge passes");
 constexpr int kDppWaveShr1 = 0x138;     // DPP control: whole-wave shift right by one lane
 constexpr int kG = 16;                  // width of the FP64 edge dot-product groups
 constexpr int64_t kGroupBands = 64;     // row bands per group of the tile order
@@ -228,10 +230,10 @@ __device__ __forceinline__ void join_tile(const Fp32Slot& sl, int64_t band, int6
     const int m = sl.m;
 
     double* wv = lds;                                  // m doubles: one centred window
-    // kTC + kB floats, 16-byte aligned: edge[t] = cov(i0, j0 + 1 + t), then
-    // kB zeros, which lanes 1..63 read in place of the edge
-    float* edge = reinterpret_cast<float*>(reinterpret_cast<char*>(lds) + edge_offset(m));
-    float* zeros = edge + kTC + kB;
+    // then, 16-byte aligned, kB zeros, which lanes 1..63 read in place of the
+    // edge, and the chunk's width + kB floats: edge[t] = cov(i0, j0 + 1 + t)
+    float* zeros = reinterpret_cast<float*>(reinterpret_cast<char*>(lds) + edge_offset(m));
+    float* edge = zeros + kB;
     if (threadIdx.x < kB) zeros[threadIdx.x] = 0.f;  // the edge's barriers below publish them
 
     const int lane = threadIdx.x;
@@ -252,18 +254,23 @@ __device__ __forceinline__ void join_tile(const Fp32Slot& sl, int64_t band, int6
         }
         const double sa = wave_sum(part);
         __syncthreads();
-        const int64_t cbase = j0 + (int64_t)lane * kQ;
+        // kEdgePass columns per pass, kQ consecutive columns per lane
+        for (int p = 0; p < kTC / kEdgePass; ++p) {
+            const int64_t p0 = j0 + (int64_t)p * kEdgePass;
+            if (p0 >= jend) break;  // uniform
+            const int64_t cbase = p0 + (int64_t)lane * kQ;
 #pragma unroll
-        for (int h = 0; h < kQ; h += kG) {
-            if (cbase + h >= jend) break;  // columns past the chunk are never swept
-            double acc[kG];
-            sliding_dots_rows<kG>(bxt, sl.bnb16, j0 + h, wv, m, acc);  // lane's columns from cbase + h
+            for (int h = 0; h < kQ; h += kG) {
+                if (cbase + h >= jend) break;  // columns past the chunk are never swept
+                double acc[kG];
+                sliding_dots_rows<kG>(bxt, sl.bnb16, p0 + h, wv, m, acc);  // lane's columns from cbase + h
 #pragma unroll
-            for (int g = 0; g < kG; ++g) {
-                const int64_t j = cbase + h + g;
-                const double mb = j < WB ? bmu[j] : 0.0;
-                const int t = lane * kQ + h + g - 1;  // edge[] starts at column j0 + 1
-                if (t >= 0) edge[t] = (float)(acc[g] - mb * sa);
+                for (int g = 0; g < kG; ++g) {
+                    const int64_t j = cbase + h + g;
+                    const double mb = j < WB ? bmu[j] : 0.0;
+                    const int t = p * kEdgePass + lane * kQ + h + g - 1;  // edge[] starts at column j0 + 1
+                    if (t >= 0) edge[t] = (float)(acc[g] - mb * sa);
+                }
             }
         }
         __syncthreads();
@@ -599,21 +606,23 @@ int fp32_reduce_parts(const unsigned long long* part, int64_t nparts, int64_t WA
     return ABJ_OK;
 }
 
-size_t fp32_chunk_bytes(int32_t n_seg, int64_t n)
+size_t fp32_chunk_bytes(int32_t n_seg, int64_t n, int32_t max_w)
 {
-    const int64_t most = n / kTC + (n_seg > 0 ? n_seg : 1) + 1;
+    const int64_t cap = max_w > 0 && max_w < kTC ? max_w : kTC;
+    const int64_t most = n / cap + (n_seg > 0 ? n_seg : 1) + 1;
     const size_t bounds = sizeof(int64_t) * (size_t)((n_seg > 0 ? n_seg : 0) + 1);
     return (bounds + sizeof(int32_t) * 2 * (size_t)most + 255) & ~size_t(255);
 }
 
-std::vector<int32_t> fp32_chunk_list(const int64_t* bounds, int32_t n_seg, int64_t n, int32_t m)
+std::vector<int32_t> fp32_chunk_list(const int64_t* bounds, int32_t n_seg, int64_t n, int32_t m, int32_t max_w)
 {
     std::vector<int32_t> c;
+    const int64_t cap = max_w > 0 && max_w < kTC ? max_w : kTC;
     auto split = [&](int64_t a, int64_t cnt) {
         // equal widths, a multiple of 16 except the last, so that no tile is a sliver
-        const int64_t k = (cnt + kTC - 1) / kTC;
+        const int64_t k = (cnt + cap - 1) / cap;
         int64_t w = (cnt + k - 1) / k;
-        w = std::min<int64_t>((w + kB - 1) / kB * kB, kTC);
+        w = std::min<int64_t>((w + kB - 1) / kB * kB, cap);
         for (int64_t s = 0; s < cnt; s += w) {
             c.push_back((int32_t)(a + s));
             c.push_back((int32_t)(a + std::min(cnt, s + w)));
@@ -631,9 +640,9 @@ std::vector<int32_t> fp32_chunk_list(const int64_t* bounds, int32_t n_seg, int64
 }
 
 int fp32_chunks_upload(const int64_t* bounds, int32_t n_seg, int64_t n, int32_t m, Arena& ar, SeriesDev* B,
-                       hipStream_t stream, int64_t** dbounds)
+                       hipStream_t stream, int64_t** dbounds, int32_t max_w)
 {
-    const std::vector<int32_t> c = fp32_chunk_list(bounds, n_seg, n, m);
+    const std::vector<int32_t> c = fp32_chunk_list(bounds, n_seg, n, m, max_w);
     // one copy: the segment bounds (when asked for), then the chunk list
     const size_t nb = (dbounds && n_seg > 0) ? (size_t)(n_seg + 1) : 0;
     std::vector<int64_t> buf(nb + (c.size() + 1) / 2, 0);
@@ -643,27 +652,32 @@ int fp32_chunks_upload(const int64_t* bounds, int32_t n_seg, int64_t n, int32_t 
     if (dbounds) *dbounds = nb ? d : nullptr;
     B->chunks = reinterpret_cast<int32_t*>(d + nb);
     B->nchunks = (int64_t)c.size() / 2;
+    B->chunk_w = fp32_chunk_width(c);
     if (!buf.empty())
         ABJ_HIP(hipMemcpyAsync(d, buf.data(), sizeof(int64_t) * buf.size(), hipMemcpyHostToDevice, stream));
     return ABJ_OK;
 }
 
-size_t fp32_lds_bytes(int max_m) { return edge_offset(max_m) + sizeof(float) * (kTC + 2 * kB); }
+size_t fp32_lds_bytes(int max_m, int max_w)
+{
+    const int w = max_w > 0 && max_w < kTC ? max_w : kTC;
+    return edge_offset(max_m) + sizeof(float) * (w + 2 * kB);
+}
 
-int join_fp32_batch(const Fp32Slot* slots_dev, int nslots, int64_t ntiles, int max_m, int64_t pairs,
+int join_fp32_batch(const Fp32Slot* slots_dev, int nslots, int64_t ntiles, int max_m, int max_w, int64_t pairs,
                     unsigned long long* counter_dev, hipStream_t stream, bool self, bool counter_zeroed)
 {
     if (ntiles <= 0) return ABJ_OK;
     if (!counter_zeroed) ABJ_TRY(fill_u64(counter_dev, kTileCounterBytes / 8, 0ull, stream));
     // enough one-wave workgroups to fill every SIMD four deep, never more than tiles
-    const int64_t grid = ntiles < 4096 ? ntiles : 4096;
+    const int64_t grid = ntiles < kFp32Grid ? ntiles : kFp32Grid;
     ProfMark mark;
     ABJ_TRY(prof_begin(&mark, stream));
     if (self)
-        hipLaunchKernelGGL(k_join_fp32_batch<true>, dim3((unsigned)grid), dim3(kWave), fp32_lds_bytes(max_m),
+        hipLaunchKernelGGL(k_join_fp32_batch<true>, dim3((unsigned)grid), dim3(kWave), fp32_lds_bytes(max_m, max_w),
                            stream, slots_dev, nslots, ntiles, counter_dev);
     else
-        hipLaunchKernelGGL(k_join_fp32_batch<false>, dim3((unsigned)grid), dim3(kWave), fp32_lds_bytes(max_m),
+        hipLaunchKernelGGL(k_join_fp32_batch<false>, dim3((unsigned)grid), dim3(kWave), fp32_lds_bytes(max_m, max_w),
                            stream, slots_dev, nslots, ntiles, counter_dev);
     ABJ_HIP(hipGetLastError());
     return prof_end(&mark, stream, pairs);

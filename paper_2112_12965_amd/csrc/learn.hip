@@ -207,7 +207,7 @@ int self_join_launch(const SeriesDev& T, int64_t excl, unsigned long long* keys,
     fp32_slot(T, T, keys, 0, &sl);
     sl.excl = excl;
     ABJ_HIP(hipMemcpyAsync(dslot, &sl, sizeof(sl), hipMemcpyHostToDevice, stream));
-    ABJ_TRY(join_fp32_batch(dslot, 1, fp32_slot_tiles(sl), T.m, sl.pairs, counter, stream, true));
+    ABJ_TRY(join_fp32_batch(dslot, 1, fp32_slot_tiles(sl), T.m, T.chunk_w, sl.pairs, counter, stream, true));
     return finalize_launch(T, T, keys, P, I, stream, P64, excl, pearson);
 }
 
@@ -228,7 +228,10 @@ int check_self_args(const double* x, int64_t n, int32_t m, const abj_opts* opts)
 int series_stats(const double* x, int64_t n, int32_t m, Arena& ar, SeriesDev* T, hipStream_t stream)
 {
     stats_carve(ar, n, m, T);
-    ABJ_TRY(fp32_chunks_upload(nullptr, 0, n, m, ar, T, stream));
+    // the chunk width of a join of the series with itself (fp32_wide_chunks)
+    const int64_t W = n - m + 1;
+    const bool wide = fp32_wide_chunks(W, (int64_t)fp32_chunk_list(nullptr, 0, n, m).size() / 2);
+    ABJ_TRY(fp32_chunks_upload(nullptr, 0, n, m, ar, T, stream, nullptr, wide ? 0 : kFp32NarrowChunk));
     T->nvalid = T->W;
     int64_t* db = ar.take<int64_t>(2);
     const int64_t hb[2] = {0, n};
@@ -238,7 +241,7 @@ int series_stats(const double* x, int64_t n, int32_t m, Arena& ar, SeriesDev* T,
 
 size_t series_stats_bytes(int64_t n, int64_t W)
 {
-    return stats_scratch_bytes(n, W) + al256(2 * sizeof(int64_t)) + fp32_chunk_bytes(0, n);
+    return stats_scratch_bytes(n, W) + al256(2 * sizeof(int64_t)) + fp32_chunk_bytes(0, n, kFp32NarrowChunk);
 }
 
 // State of one dict_build call.
@@ -306,7 +309,7 @@ int e_max_of(Learner& L, const std::vector<Seg>& segs, double* out)
     Fp32Slot sl;
     fp32_slot(L.ts, B, L.keys, 0, &sl);
     ABJ_HIP(hipMemcpyAsync(L.slot, &sl, sizeof(sl), hipMemcpyHostToDevice, L.stream));
-    ABJ_TRY(join_fp32_batch(L.slot, 1, fp32_slot_tiles(sl), L.m, sl.pairs, L.counter, L.stream));
+    ABJ_TRY(join_fp32_batch(L.slot, 1, fp32_slot_tiles(sl), L.m, B.chunk_w, sl.pairs, L.counter, L.stream));
     ABJ_TRY(finalize_launch(L.ts, B, L.keys, L.P, L.I, L.stream, L.P64));
     ABJ_TRY(fill_u64(L.red + 2, 2, 0ull, L.stream));
     hipLaunchKernelGGL(k_max_nan, dim3(grid_of(L.W)), dim3(kBlock), 0, L.stream, L.P64, L.W, L.red + 2);

@@ -39,8 +39,23 @@ using namespace abj;
 namespace abj {
 struct DictM {
     int32_t m = 0;
-    SeriesDev B;
+    SeriesDev B;  // with the wide FP32 chunk list
     void* mem = nullptr;
+    // the narrow FP32 chunk list (kFp32NarrowChunk windows at most)
+    const int32_t* narrow_chunks = nullptr;
+    int64_t narrow_nchunks = 0;
+    int32_t narrow_w = 0;
+    // the reference side of an FP32 join of WA query windows (fp32_wide_chunks)
+    SeriesDev fp32_side(int64_t WA) const
+    {
+        SeriesDev b = B;
+        if (!fp32_wide_chunks(WA, B.nchunks)) {
+            b.chunks = narrow_chunks;
+            b.nchunks = narrow_nchunks;
+            b.chunk_w = narrow_w;
+        }
+        return b;
+    }
     // the 16-bit tiers' dictionary side (operand fragments and block masks),
     // one per tier (0 = BF16, 1 = FP16), built at its first use
     mutable void* op_mem[2] = {nullptr, nullptr};
@@ -183,7 +198,8 @@ extern "C" int abj_dict_create(const double* dict, int64_t n_dict, const int64_t
             DictM e;
             e.m = ms[a];
             const int64_t W = n_dict >= e.m ? n_dict - e.m + 1 : 0;
-            const size_t bytes = stats_scratch_bytes(n_dict, W) + fp32_chunk_bytes(n_seg, n_dict);
+            const size_t bytes = stats_scratch_bytes(n_dict, W) + fp32_chunk_bytes(n_seg, n_dict) +
+                                 fp32_chunk_bytes(n_seg, n_dict, kFp32NarrowChunk);
             if (hipMalloc(&e.mem, bytes) != hipSuccess) {
                 rc = set_error(ABJ_ENOMEM, "dictionary statistics allocation failed");
                 break;
@@ -192,6 +208,14 @@ extern "C" int abj_dict_create(const double* dict, int64_t n_dict, const int64_t
             stats_carve(ar, n_dict, e.m, &e.B);
             rc = fp32_chunks_upload(seg_bounds, n_seg, n_dict, e.m, ar, &e.B, st);
             if (rc != ABJ_OK) break;
+            {
+                SeriesDev narrow;
+                rc = fp32_chunks_upload(seg_bounds, n_seg, n_dict, e.m, ar, &narrow, st, nullptr, kFp32NarrowChunk);
+                if (rc != ABJ_OK) break;
+                e.narrow_chunks = narrow.chunks;
+                e.narrow_nchunks = narrow.nchunks;
+                e.narrow_w = narrow.chunk_w;
+            }
             for (int32_t sgi = 0; sgi < n_seg; ++sgi) {
                 const int64_t len = seg_bounds[sgi + 1] - seg_bounds[sgi];
                 if (len >= e.m) e.B.nvalid += len - e.m + 1;
@@ -278,14 +302,15 @@ extern "C" int ab_join_dict(const abj_dict* d, const double* query, int64_t n_qu
     ABJ_TRY(ensure_device());
     hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
     Arena ar(stream);
-    // per-chunk keys instead of atomics when the chunk list is short
-    const size_t part_bytes =
-        o.tier == ABJ_TIER_FP32 && e->B.W > 0 ? fp32_partial_bytes(WA, e->B.nchunks) : 0;
-    ar.reserve(query_scratch_bytes(n_query, m, e->B.W, o, plan) + part_bytes);
+    // FP32: the chunk list for this join's size; per-chunk keys instead of
+    // atomics when that list is short
+    const SeriesDev B = o.tier == ABJ_TIER_FP32 ? e->fp32_side(WA) : e->B;
+    const size_t part_bytes = o.tier == ABJ_TIER_FP32 && B.W > 0 ? fp32_partial_bytes(WA, B.nchunks) : 0;
+    ar.reserve(query_scratch_bytes(n_query, m, B.W, o, plan) + part_bytes);
     ABJ_TRY(ar.commit());
     MfmaDictOp dop;
     if (o.tier != ABJ_TIER_FP32) ABJ_TRY(dict_operand(d, e, o.tier, stream, &dop));
-    return join_query(query, n_query, m, e->B, o, plan, P_AB, I_AB, ar, stream, part_bytes,
+    return join_query(query, n_query, m, B, o, plan, P_AB, I_AB, ar, stream, part_bytes,
                       o.tier != ABJ_TIER_FP32 ? &dop : nullptr);
 }
 
@@ -495,7 +520,7 @@ int launch_batch(abj_server* s, Batch& b)
 
     size_t qo = tables, po = up, io = up + pbytes, wo = up + down;
     int64_t blk_sum = 0, blk_loc = 0, blk_win = 0, blk_fin = 0, tiles = 0, pairs = 0;
-    int max_m = 2;
+    int max_m = 2, max_w = 0;
     std::vector<MfmaBatchItem> items(fp32 ? 0 : k);
     for (size_t a = 0; a < k; ++a) {
         Req* r = b.reqs[a];
@@ -534,7 +559,9 @@ int launch_batch(abj_server* s, Batch& b)
         stats_carve_job(ar, r->dq, r->n, r->m, &r->A, r->keys, H + a * stats_job_bytes(), &blk_sum, &blk_loc,
                         &blk_win);
         Fp32Slot sl;
-        fp32_slot(r->A, r->dm->B, r->keys, tiles, &sl);
+        const SeriesDev side = r->dm->fp32_side(r->W);
+        fp32_slot(r->A, side, r->keys, tiles, &sl);
+        max_w = std::max(max_w, (int)side.chunk_w);
         tiles += fp32_slot_tiles(sl);
         pairs += sl.pairs;
         max_m = std::max(max_m, (int)r->m);
@@ -548,7 +575,7 @@ int launch_batch(abj_server* s, Batch& b)
     ABJ_HIP(hipMemcpyAsync(D, H, up, hipMemcpyHostToDevice, st));
     if (fp32) {
         ABJ_TRY(stats_launch_many(D, (int)k, blk_sum, blk_loc, blk_win, st));
-        ABJ_TRY(join_fp32_batch(reinterpret_cast<const Fp32Slot*>(D + t_stats), (int)k, tiles, max_m, pairs,
+        ABJ_TRY(join_fp32_batch(reinterpret_cast<const Fp32Slot*>(D + t_stats), (int)k, tiles, max_m, max_w, pairs,
                                 reinterpret_cast<unsigned long long*>(D + tables - kTileCounterBytes), st, false,
                                 true));
         ABJ_TRY(finalize_launch_many(D + t_stats + t_slots, (int)k, blk_fin, st));
